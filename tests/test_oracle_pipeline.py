@@ -1,0 +1,145 @@
+"""Pins for the oracle's full pipeline: condense -> assemble -> solve -> recover.
+
+* exact Helmholtz solutions: sin(kappa x1) (the tiny workload), the paper's
+  J0(kappa |x - (-0.1, 0.5)|) (Sec. 3, eq. (constant_coeff_helm)) and the
+  plane wave on the quarter annulus;
+* brute force: the dense solve of the full unreduced collocation system
+  equals the condensed route (static condensation is exact block
+  elimination);
+* the spectral convergence rate in p;
+* the Dirichlet-to-Neumann property of S for plane waves;
+* the paper's accuracy level at 10 points per wavelength (Sec. 3.1).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import interface as itf
+from oracle import leaf as lf
+from paper_2211_14969_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def j0_problem(p, n, kappa, centre=(-0.1, 0.5)):
+    cx, cy = centre
+    sol = lambda x, y, xp: scipy.special.j0(kappa * np.sqrt((x - cx) ** 2 + (y - cy) ** 2))
+    return inputs.Problem(name="j0", nx=n, ny=n, p=p, kappa=kappa,
+                          coef={"k2b": lambda x, y, xp: xp.zeros_like(x) + kappa * kappa},
+                          g=sol, exact=sol)
+
+
+def test_tiny_workload_exact_solution():
+    prob = inputs.tiny()
+    assert (prob.nx, prob.ny, prob.p, prob.kappa) == (4, 4, 8, 10.0)
+    sol = itf.solve(prob)
+    assert sol.num.nunknown == 144
+    assert itf.relerr_true(sol, prob) < 1e-3
+
+
+@pytest.mark.parametrize("p,tol", [(8, 1e-3), (12, 1e-7), (16, 1e-10)])
+def test_j0_exact_solution(p, tol):
+    prob = j0_problem(p, 4, 10.0)
+    assert itf.relerr_true(itf.solve(prob), prob) < tol
+
+
+@pytest.mark.parametrize("p,tol", [(8, 2e-2), (12, 1e-4), (16, 1e-7)])
+def test_annulus_plane_wave(p, tol):
+    prob = inputs.annulus(p=p, ntheta=4, nr=2, kappa=10.0)
+    assert itf.relerr_true(itf.solve(prob), prob) < tol
+
+
+@pytest.mark.parametrize("maker", [lambda: inputs.tiny(),
+                                   lambda: inputs.single_bump(p=10, n=3, kappa=20.0),
+                                   lambda: inputs.annulus(p=8, ntheta=3, nr=2, kappa=12.0),
+                                   lambda: inputs.multi_bump(p=9, n=2, kappa=30.0)])
+def test_brute_force_full_system(maker):
+    prob = maker()
+    leaves = itf.build_leaves(prob)
+    sol = itf.solve(prob, leaves)
+    A, b, num = itf.full_system(prob, leaves)
+    u_brute = np.linalg.solve(A, b)
+    u_cond = itf.stack_full(sol)
+    assert np.linalg.norm(u_cond - u_brute) <= 1e-10 * np.linalg.norm(u_brute)
+    assert itf.relerr_res(A, b, u_cond) < 1e-10
+
+
+def test_brute_force_with_body_load():
+    """f != 0 exercises h and w: manufactured u = sin(3x) cos(2y) + x y with
+    b == 1 and kappa = 4, f = -Lap u - kappa^2 u."""
+    kappa = 4.0
+    u = lambda x, y, xp: xp.sin(3 * x) * xp.cos(2 * y) + x * y
+    f = lambda x, y, xp: (13.0 - kappa ** 2) * xp.sin(3 * x) * xp.cos(2 * y) - kappa ** 2 * x * y
+    prob = inputs.Problem(name="mf", nx=3, ny=2, p=12, kappa=kappa,
+                          coef={"k2b": lambda x, y, xp: xp.zeros_like(x) + kappa ** 2},
+                          g=u, exact=u, f=f)
+    leaves = itf.build_leaves(prob)
+    sol = itf.solve(prob, leaves)
+    A, b, _ = itf.full_system(prob, leaves)
+    u_brute = np.linalg.solve(A, b)
+    assert np.linalg.norm(itf.stack_full(sol) - u_brute) <= 1e-10 * np.linalg.norm(u_brute)
+    assert itf.relerr_true(sol, prob) < 1e-8
+
+
+def test_spectral_convergence_in_p():
+    errs = {}
+    for p in range(6, 18, 2):
+        prob = inputs.tiny(p=p)
+        errs[p] = itf.relerr_true(itf.solve(prob), prob)
+    for p in range(6, 14, 2):
+        if errs[p] < 1e-10:
+            break
+        assert errs[p + 2] <= 0.1 * errs[p], errs
+    assert errs[16] <= 1e-10, errs
+
+
+@pytest.mark.parametrize("p", [16, 20])
+def test_dtn_plane_waves(p):
+    """b == 1: S maps the trace of cos(kappa x.d) to its outward normal derivative."""
+    box = (0.25, 0.5, 0.5, 0.75)
+    X, Y = lf.grid(box, p)
+    B = lf.flat(p, lf.boundary_nodes(p))
+    m = p - 2
+    for kappa in (5.0, 10.0):
+        c = lf.condense(lf.blocks(box, p, {"k2b": np.full(p * p, kappa ** 2)}))
+        for phi in np.linspace(0.0, 2 * np.pi, 7):
+            d = (math.cos(phi), math.sin(phi))
+            ph = kappa * (X * d[0] + Y * d[1])
+            u, ux, uy = np.cos(ph), -kappa * d[0] * np.sin(ph), -kappa * d[1] * np.sin(ph)
+            dn = np.concatenate([-ux[B[:m]], ux[B[m:2 * m]], -uy[B[2 * m:3 * m]], uy[B[3 * m:]]])
+            assert np.linalg.norm(c.S @ u[B] - dn) <= 1e-10 * np.linalg.norm(dn)
+
+
+@pytest.mark.slow
+def test_paper_accuracy_level_p22_10ppw():
+    """At 10 points per wavelength and p = 22 the paper reports 6 true digits
+    for problems of up to 5 million nodes; on a smaller grid (less pollution)
+    the oracle must do at least as well."""
+    lv = json.load(open(os.path.join(GOLDEN, "paper_levels.json")))
+    digits = lv["p22_true_digits_10ppw"]["value"]
+    p, n = 22, 4
+    N = n * n * p * p
+    kappa = 2 * math.pi * math.sqrt(N) / 10.0      # 10 points per wavelength
+    prob = j0_problem(p, n, kappa, centre=tuple(lv["j0_source_point"]["value"]))
+    err = itf.relerr_true(itf.solve(prob), prob)
+    assert err <= 10.0 ** (-digits + 1)
+
+
+def test_planted_flux_sign_breaks_brute_force_agreement(monkeypatch):
+    """A sign slip in one edge's flux rows makes the reduced system wrong;
+    the exact-solution pin catches it."""
+    orig = lf.operator
+
+    def bad(box, p, coef):
+        L = orig(box, p, coef)
+        for i in range(1, p - 1):
+            L[i + p * (p - 1)] *= -1.0      # N edge
+        return L
+
+    monkeypatch.setattr(lf, "operator", bad)
+    prob = inputs.tiny(p=10)
+    assert itf.relerr_true(itf.solve(prob), prob) > 1e-2
