@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Throughput of batched HPS leaf condensation on one MI355X.
+
+One step = one pass of the whole hot path over the batch: form every leaf's
+collocation operator on the device, factor A_ii, solve for X = A_ii^{-1} A_ib
+and form S = A_bb - A_bi X (plus the FP64 refinement of X in the mixed
+precision mode).  Inputs (leaf boxes, coefficient samples) are resident in
+HBM before the timed region; nothing is copied to or from the host inside it.
+
+Workload: the unit square split into 64 x 64 leaves of order p = 16,
+kappa = 100, b(x) = 1 - 0.5 exp(-|x - (0.5, 0.5)|^2 / 0.05), in FP64.  The
+same batch is also condensed in FP32 + FP64 refinement and compared against
+the FP64 result; the plain FP64 CPU oracle is timed on a bounded sample of
+the same leaves.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def algorithmic_flops(p: int):
+    """Useful FLOP per leaf, per kernel: LU of A_ii together with the forward
+    elimination of the nb columns of A_ib (2/3 ni^3 + ni^2 nb), the back
+    substitution (ni^2 nb), and S with A_bi's p-2 nonzeros per row
+    (2 nb^2 (p-2))."""
+    ni, nb = (p - 2) ** 2, 4 * (p - 2)
+    factor = (2.0 / 3.0) * ni ** 3 + ni * ni * nb
+    back = ni * ni * nb
+    schur = 2.0 * nb * nb * (p - 2)
+    return {"factor": factor, "backsolve": back, "schur": schur,
+            "total": factor + back + schur}
+
+
+def cpu_baseline(problem, seconds: float):
+    """Time the FP64 CPU oracle (operator build + LAPACK condensation) on
+    consecutive leaves of the workload until `seconds` have elapsed."""
+    import numpy as np
+    from oracle import leaf as lf
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    boxes = problem.boxes()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        box = boxes[n % problem.nleaf]
+        coef = lf.sample_coefficients(problem, box, problem.p)
+        lf.condense(lf.blocks(box, problem.p, coef))
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds and n >= 4:
+            break
+    return {"value": n / el, "unit": "leaves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} consecutive leaves of the same workload, {el:.1f} s, "
+                      f"operator build + LU condensation per leaf in numpy/LAPACK FP64",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", choices=("fp64", "fp32"), default="fp64",
+                    help="precision of the timed path (fp32 = FP32 + FP64 refinement)")
+    ap.add_argument("--max-refine", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32+refinement comparison run")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: leaves are independent, so a multi-GPU run "
+              "would shard the batch; that path is not built (use --gpus 1).", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2211_14969_amd import hps, inputs
+    from paper_2211_14969_amd.harness import LeafBatch
+
+    if not torch.cuda.is_available():
+        print("no ROCm device visible", file=sys.stderr)
+        return 1
+    hps.load()
+    prob = inputs.single_bump()
+    p, L = prob.p, prob.nleaf
+    print(f"# workload {prob.name}: {L} leaves, p={p}", file=sys.stderr, flush=True)
+    B = LeafBatch([prob])
+    S, w, info = B.alloc_outputs()
+    prec = hps.HPS_FP64 if args.prec == "fp64" else hps.HPS_FP32_REFINE
+
+    def step(pr=prec, S_=S):
+        hps.hps_leaf_condense(B.batch, pr, 0.0, args.max_refine, None, S_, w, info, 0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = hps.hps_leaf_condense(B.batch, prec, 0.0, args.max_refine, None, S, w, info, hps.HPS_SYNC)
+    print(f"# warmup done, status {st}", file=sys.stderr, flush=True)
+
+    hps.hps_ctx_set_timing(B.ctx, True)
+    hps.hps_ctx_phase_times(B.ctx)          # reset
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    phases = hps.hps_ctx_phase_times(B.ctx)
+    hps.hps_ctx_set_timing(B.ctx, False)
+    bad = int((info != 0).sum().item())
+
+    fl = algorithmic_flops(p)
+    f_ms, f_n = phases["factor"]
+    t_factor = f_ms / max(f_n, 1)
+    dtype = "f64" if args.prec == "fp64" else "f32+f64"
+    peak = PEAK_TFLOPS["fp64" if args.prec == "fp64" else "fp32"]
+    achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
+    value = L / (ms * 1e-3)
+    line = {
+        "metric": "leaf condensations/s + % MFMA peak; FP64 vs FP32+refine at <=1e-9 rel err",
+        "value": value,
+        "unit": "leaves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": prob.name, "leaves": L, "p": p, "kappa": prob.kappa,
+                   "b": prob.meta.get("b"), "precision": args.prec, "parallelism": "single-gpu"},
+        "useful_tflops": fl["total"] * L / (ms * 1e-3) / 1e12,
+        "useful_frac_fp64_peak": fl["total"] * L / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items() if v[1]},
+        "leaves_with_nonzero_info": bad,
+        "roofline": {"bound": "mfma", "kernel": "k_factor", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "per_launch_flop": fl["factor"] * L, "launch_ms": t_factor},
+    }
+
+    if not args.no_compare:
+        other = hps.HPS_FP32_REFINE if prec == hps.HPS_FP64 else hps.HPS_FP64
+        S2 = torch.empty_like(S)
+        for _ in range(2):
+            step(other, S2)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        n2 = max(3, args.steps // 2)
+        e0.record()
+        for _ in range(n2):
+            step(other, S2)
+        e1.record()
+        torch.cuda.synchronize()
+        ms2 = e0.elapsed_time(e1) / n2
+        nb = 4 * (p - 2)
+        Sa, Sb = S.view(L, nb, nb), S2.view(L, nb, nb)
+        rel = ((Sa - Sb).flatten(1).norm(dim=1) / Sa.flatten(1).norm(dim=1)).max().item()
+        line["compare"] = {"precision": "fp32+refine" if other == hps.HPS_FP32_REFINE else "fp64",
+                           "leaves_per_s": L / (ms2 * 1e-3), "ms_per_step": ms2,
+                           "max_refine": args.max_refine,
+                           "max_leaf_relerr_S_vs_other": rel}
+
+    if not args.no_cpu:
+        print("# timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    B.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

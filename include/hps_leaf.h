@@ -1,0 +1,196 @@
+/*
+ * hps_leaf.h - batched leaf-level static condensation for the Hierarchical
+ * Poincare-Steklov (HPS) discretisation on AMD Instinct MI355X (gfx950).
+ *
+ * Reference: A. Yesypenko, P.-G. Martinsson, "GPU Optimizations for the
+ * Hierarchical Poincare-Steklov Scheme", arxiv 2211.14969.
+ *
+ * The problem (Sec. 1, eqs. (bvp), (var_helm)): A u = f in a domain, u = g on
+ * its boundary, with A a second-order elliptic operator.  In the reference
+ * coordinates of a leaf box this library collocates
+ *
+ *     A u = -(a11 u_11 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u
+ *
+ * (the variable-coefficient Helmholtz operator has a11 = a22 = 1,
+ * c1 = c2 = 0, k2b = kappa^2 b).  The mixed term a12 u_12 is not supported.
+ *
+ * Discretisation (Sec. 2): each leaf carries a p x p tensor grid of Chebyshev
+ * extreme points; the PDE is collocated at the (p-2)^2 interior nodes by
+ * spectral differentiation, and the outward normal derivative (the flux that
+ * must be continuous between neighbouring leaves) is taken at the 4(p-2)
+ * edge nodes.  Corners are not used.  Static condensation (Sec. 2, before
+ * eq. (hps_reduced)) eliminates the interior nodes:
+ *
+ *     X = A_ii^{-1} A_ib,  h = A_ii^{-1} f_i,  S = A_bb - A_bi X,  w = A_bi h,
+ *
+ * and after the reduced system is solved the interior values are recovered
+ * as u_i = h - X u_b (Sec. 3, text after eq. (constant_coeff_helm)).
+ *
+ * Layouts (all arrays row-major, leaves concatenated in group order):
+ *   node (i, j) of a leaf, i along x1, j along x2, has flat index i + p*j;
+ *   interior order: (i, j), 1 <= i, j <= p-2, i fastest       -> ni = (p-2)^2
+ *   boundary order: W (i=0, j up), E (i=p-1, j up),
+ *                   S (j=0, i up), N (j=p-1, i up)            -> nb = 4(p-2)
+ *   flux sign: outward (W: -d/dx1, E: +d/dx1, S: -d/dx2, N: +d/dx2).
+ *
+ * Memory: every array argument is caller-owned DEVICE memory unless stated
+ * otherwise, and must stay valid until the context stream has executed the
+ * call.  Calls are asynchronous on the context stream; argument errors are
+ * detected on the host, returned synchronously, and nothing is enqueued.
+ * No C++ exception crosses this interface.  Device-side failures are written
+ * per leaf into `info` and are folded into the return code only with
+ * HPS_SYNC.
+ */
+#ifndef HPS_LEAF_H
+#define HPS_LEAF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPS_OK = 0,
+  HPS_ERR_INVALID = -1,       /* bad argument; nothing was enqueued            */
+  HPS_ERR_OOM = -2,           /* device allocation failed                      */
+  HPS_ERR_HIP = -3,           /* a HIP runtime call failed                     */
+  HPS_ERR_SINGULAR = -4,      /* (HPS_SYNC) some leaf had an exactly zero pivot */
+  HPS_ERR_NOT_CONVERGED = -5, /* (HPS_SYNC) refinement did not reach `tol`     */
+  HPS_ERR_NONFINITE = -6      /* (HPS_SYNC) a leaf produced Inf or NaN         */
+} hps_status;
+
+typedef enum {
+  HPS_FP64 = 0,        /* LU, triangular solves and Schur complement in FP64   */
+  HPS_FP32_REFINE = 1  /* FP32 LU and solves (MFMA), FP64 iterative refinement
+                          of X with an FP64 residual A_ib - A_ii X; S in FP64 */
+} hps_precision;
+
+/* flags */
+#define HPS_SYNC 1                /* synchronise and fold `info` into the result */
+#define HPS_RECOVER_REFACTOR 2    /* recover: re-form and re-factor the leaves
+                                     instead of using the stored X, h (the
+                                     paper's storage-free mode, Sec. 2 remark) */
+
+/* Limits of this build. */
+#define HPS_P_MIN 4
+#define HPS_P_MAX 32
+
+/* One group of leaves sharing the order p (a whole problem, or one order
+ * class of a multi-problem batch).
+ *   box : device [nleaf][4] = x0, x1, y0, y1 of each leaf (reference coords)
+ *   a11, a22, c1, c2, k2b : device [nleaf][p*p] samples at every node (flat
+ *         index i + p*j), or NULL for the default (a11 = a22 = 1, others 0).
+ *         Sample them at the coordinates returned by hps_leaf_nodes.
+ *   a12 : must be NULL (the mixed derivative is not supported).          */
+typedef struct {
+  int p;
+  int nleaf;
+  const double *box;
+  const double *a11, *a12, *a22, *c1, *c2, *k2b;
+} hps_leaf_desc;
+
+typedef struct hps_ctx hps_ctx;
+typedef struct hps_batch hps_batch;
+
+/* Create a context bound to `stream` (a hipStream_t; NULL = default stream)
+ * on the current device.  *out receives the handle. */
+hps_status hps_ctx_create(void *stream, hps_ctx **out);
+hps_status hps_ctx_destroy(hps_ctx *ctx);
+
+/* Set up a batch of leaf groups: validates the descriptors, builds the
+ * Chebyshev tables for each order (Sec. 2: p x p Chebyshev grid and spectral
+ * differentiation) and allocates the batch's device workspace (LU workspace
+ * for the leaves in flight, the FP64 X and h kept for recovery).  The
+ * descriptor arrays are only read when the batch is used, so they must stay
+ * valid for the batch's lifetime.  Synchronous. */
+hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups,
+                          hps_batch **out);
+
+/* Total number of leaves, and ni / nb of group g. */
+int hps_batch_nleaf(const hps_batch *b);
+hps_status hps_batch_group_dims(const hps_batch *b, int g, int *p, int *nleaf,
+                                int *ni, int *nb);
+
+/* Write the physical coordinates of every node of group g:
+ * xy device [nleaf][p*p][2].  Async. */
+hps_status hps_leaf_nodes(hps_batch *b, int g, double *xy);
+
+/* Write the dense leaf blocks of group g (Sec. 2: the p^2 x p^2 leaf matrix,
+ * partitioned into interior / boundary):  Aii [nleaf][ni][ni],
+ * Aib [nleaf][ni][nb], Abi [nleaf][nb][ni], Abb [nleaf][nb][nb];
+ * any pointer may be NULL.  For checking the operator; the condensation
+ * itself never materialises A_bi or A_bb.  Async. */
+hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib,
+                             double *Abi, double *Abb);
+
+/* Static condensation of every leaf (Sec. 2; cost O(p^4 N), Sec. 2 batching
+ * paragraph): forms the leaf operator on the device, factors A_ii with
+ * partial pivoting, computes X (and h when f != NULL), refines X in FP64
+ * when prec == HPS_FP32_REFINE, and forms S and w in FP64.
+ *   prec       : HPS_FP64 or HPS_FP32_REFINE
+ *   tol        : refinement stop test on the normwise backward error of the
+ *                FP64 residual r = A_ib - A_ii X (per leaf):
+ *                ||r||_F / (||A_ii||_F ||X||_F + ||[A_ib f_i]||_F) <= tol.
+ *                Ignored for HPS_FP64.  <= 0 selects ni * 2^-53.
+ *   max_refine : FP32 correction steps at most (HPS_FP32_REFINE), 0..16.
+ *                The residual is evaluated before each correction and once
+ *                more after the last one; a leaf stops as soon as it passes,
+ *                and is flagged -1 if it never does.
+ *   f          : device [total leaves][ni] interior body load, or NULL (f = 0)
+ *   S          : device [total leaves][nb][nb]   (output)
+ *   w          : device [total leaves][nb] or NULL (output; 0 when f == NULL)
+ *   info       : device [total leaves] or NULL (output):
+ *                0 ok; k > 0 exact zero pivot in column k (1-based, LAPACK
+ *                getrf convention); -1 refinement did not meet tol;
+ *                -2 non-finite value in X or S.
+ *   flags      : HPS_SYNC or 0
+ * The stored X and h are kept in the batch for hps_leaf_recover.  Async
+ * unless HPS_SYNC. */
+hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol,
+                             int max_refine, const double *f, double *S,
+                             double *w, int *info, int flags);
+
+/* Interior recovery (Sec. 3, after eq. (constant_coeff_helm)):
+ *   ub : device [total leaves][nb]  boundary values
+ *   f  : device [total leaves][ni] or NULL; used only with
+ *        HPS_RECOVER_REFACTOR (the stored h already holds the f given to
+ *        hps_leaf_condense)
+ *   ui : device [total leaves][ni]  (output)
+ * Default: u_i = h - X u_b from the stored FP64 X and h (requires a prior
+ * hps_leaf_condense).  With HPS_RECOVER_REFACTOR: re-forms and re-factors
+ * every leaf in FP64 and solves A_ii u_i = f_i - A_ib u_b (the paper's mode:
+ * factorisations are not kept).  Async unless HPS_SYNC. */
+hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
+                            double *ui, int flags);
+
+/* Copy the stored FP64 solution operator out of the batch:
+ *   Xt : device [total leaves][nb][ni]  (X transposed: Xt[l][b][i] = X_l[i][b])
+ *   h  : device [total leaves][ni]
+ * Either may be NULL.  Async. */
+hps_status hps_batch_export(hps_batch *b, double *Xt, double *h);
+
+/* Refinement statistics of the last hps_leaf_condense (host pointer args):
+ * number of refinement steps executed. */
+hps_status hps_batch_stats(const hps_batch *b, int *refine_steps);
+
+/* Per-phase timing with HIP events on the context stream (tracing aid).
+ * While enabled, every kernel launch of hps_leaf_condense / hps_leaf_recover
+ * is bracketed by events and the elapsed time is accumulated per phase:
+ *   0 operator build   1 LU factorisation (with forward elimination of the
+ *   right-hand sides)   2 back substitution   3 refinement (residual,
+ *   forward replay, back substitution, convergence test)   4 Schur
+ *   complement   5 recovery.
+ * hps_ctx_phase_times synchronises the stream, writes the accumulated
+ * milliseconds and launch counts of the HPS_NPHASE phases (host arrays,
+ * either may be NULL) and resets them. */
+#define HPS_NPHASE 6
+hps_status hps_ctx_set_timing(hps_ctx *ctx, int enable);
+hps_status hps_ctx_phase_times(hps_ctx *ctx, double *ms, int *launches);
+
+hps_status hps_batch_destroy(hps_batch *b);
+
+const char *hps_status_string(hps_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPS_LEAF_H */

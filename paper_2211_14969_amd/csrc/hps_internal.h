@@ -1,0 +1,83 @@
+// Internal declarations shared by the HIP kernels and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace hps {
+
+// One order-p group of leaves as the kernels see it (pointers already offset
+// to the first leaf of the launch).
+struct Geom {
+  int p;        // points per direction
+  int m;        // p - 2
+  int ni;       // (p-2)^2 interior nodes
+  int nb;       // 4(p-2) edge nodes
+  int R;        // ni rounded up to 16: rows / A-part columns of the work matrix
+  int RT;       // R / 16 row tiles
+  int CT;       // column tiles of the work matrix (A part + right-hand sides)
+  int nrhs;     // right-hand-side columns in use
+  const double *box;                        // [nleaf][4]
+  const double *a11, *a22, *c1, *c2, *k2b;  // [nleaf][p*p] or nullptr
+  const double *D;                          // [p][p]  d/dt on [-1, 1]
+  const double *D2;                         // [p][p]  D*D
+};
+
+// Right-hand-side layouts of the work matrix.
+enum RhsMode : int {
+  RHS_CONDENSE = 0,  // columns: A_ib (nb), then f_i if present
+  RHS_REFACTOR = 1   // one column: f_i - A_ib u_b
+};
+
+// Where the back substitution puts its result.
+enum BackMode : int {
+  BACK_STORE = 0,    // X -> Xt (FP64, transposed), h -> h
+  BACK_ACCUM = 1,    // Xt += dX, h += dh
+  BACK_UI = 2        // single column -> ui
+};
+
+struct BackOut {
+  double *Xt;        // [nleaf][nb][ni]
+  double *h;         // [nleaf][ni]   (nullptr when no f column)
+  double *ui;        // [nleaf][ni]   (BACK_UI)
+  const int *skip;   // [nleaf] leaves to leave untouched (nullptr = none)
+  int mode;
+};
+
+constexpr int kInfoActive = 0x7fffffff;
+
+// Launchers (hps_kernels.hip).  All enqueue on `s` and return hipError_t.
+hipError_t launch_build(const Geom &g, int nleaf, int mode, bool fp32, void *M,
+                        const double *f, const double *ub, hipStream_t s);
+hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
+                         int *rstep, int *info, hipStream_t s);
+hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
+                            const int *piv, const int *rstep, const BackOut &o,
+                            hipStream_t s);
+hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M,
+                           const int *piv, const int *rstep, const int *skip,
+                           hipStream_t s);
+hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
+                           const double *h, const double *f, const int *skip,
+                           double *norms, hipStream_t s);
+hipError_t launch_convcheck(int nleaf, const double *norms, double tol, int *conv,
+                            int *info, int last, hipStream_t s);
+hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h,
+                        double *S, double *w, int *info, hipStream_t s);
+hipError_t launch_recover(const Geom &g, int nleaf, const double *Xt, const double *h,
+                          const double *ub, double *ui, hipStream_t s);
+hipError_t launch_operator(const Geom &g, int nleaf, double *Aii, double *Aib,
+                           double *Abi, double *Abb, hipStream_t s);
+hipError_t launch_nodes(const Geom &g, int nleaf, const double *t, double *xy,
+                        hipStream_t s);
+hipError_t launch_fill_int(int *dst, int n, int v, hipStream_t s);
+hipError_t launch_fill_double(double *dst, size_t n, double v, hipStream_t s);
+hipError_t launch_copy_info(const int *src, int *dst, int n, hipStream_t s);
+
+// Bytes of dynamic LDS the factor kernel needs; 0 if it does not fit.
+size_t factor_lds_bytes(const Geom &g, bool fp32);
+
+// Host tables (hps_cheb.cpp).
+void cheb_tables(int p, double *t, double *D, double *D2);
+
+}  // namespace hps

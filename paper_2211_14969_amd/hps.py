@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libhpsleaf.so (include/hps_leaf.h).
+
+Argument marshalling only: every step of the condensation runs in the HIP
+library.  Device buffers are torch tensors on a ROCm device; the library is
+bound to a torch stream.  If the shared library is missing this module
+raises at load time; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhpsleaf.so")
+
+HPS_OK = 0
+HPS_ERR_INVALID = -1
+HPS_ERR_OOM = -2
+HPS_ERR_HIP = -3
+HPS_ERR_SINGULAR = -4
+HPS_ERR_NOT_CONVERGED = -5
+HPS_ERR_NONFINITE = -6
+
+HPS_FP64 = 0
+HPS_FP32_REFINE = 1
+
+HPS_SYNC = 1
+HPS_RECOVER_REFACTOR = 2
+
+HPS_P_MIN = 4
+HPS_P_MAX = 32
+
+EXPORTED = (
+    "hps_status_string", "hps_ctx_create", "hps_ctx_destroy", "hps_leaf_build",
+    "hps_batch_nleaf", "hps_batch_group_dims", "hps_leaf_nodes", "hps_leaf_operator",
+    "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
+    "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times",
+)
+
+HPS_NPHASE = 6
+PHASES = ("build", "factor", "backsolve", "refine", "schur", "recover")
+
+
+class hps_leaf_desc(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int),
+        ("nleaf", ctypes.c_int),
+        ("box", ctypes.c_void_p),
+        ("a11", ctypes.c_void_p),
+        ("a12", ctypes.c_void_p),
+        ("a22", ctypes.c_void_p),
+        ("c1", ctypes.c_void_p),
+        ("c2", ctypes.c_void_p),
+        ("k2b", ctypes.c_void_p),
+    ]
+
+
+class HpsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (once) and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_2211_14969_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, ip, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double
+    L.hps_status_string.restype = ctypes.c_char_p
+    L.hps_status_string.argtypes = [i]
+    L.hps_ctx_create.restype = i
+    L.hps_ctx_create.argtypes = [vp, ctypes.POINTER(vp)]
+    L.hps_ctx_destroy.restype = i
+    L.hps_ctx_destroy.argtypes = [vp]
+    L.hps_leaf_build.restype = i
+    L.hps_leaf_build.argtypes = [vp, ctypes.POINTER(hps_leaf_desc), i, ctypes.POINTER(vp)]
+    L.hps_batch_nleaf.restype = i
+    L.hps_batch_nleaf.argtypes = [vp]
+    L.hps_batch_group_dims.restype = i
+    L.hps_batch_group_dims.argtypes = [vp, i] + [ctypes.POINTER(ip)] * 4
+    L.hps_leaf_nodes.restype = i
+    L.hps_leaf_nodes.argtypes = [vp, i, vp]
+    L.hps_leaf_operator.restype = i
+    L.hps_leaf_operator.argtypes = [vp, i, vp, vp, vp, vp]
+    L.hps_leaf_condense.restype = i
+    L.hps_leaf_condense.argtypes = [vp, i, d, i, vp, vp, vp, vp, i]
+    L.hps_leaf_recover.restype = i
+    L.hps_leaf_recover.argtypes = [vp, vp, vp, vp, i]
+    L.hps_batch_export.restype = i
+    L.hps_batch_export.argtypes = [vp, vp, vp]
+    L.hps_batch_stats.restype = i
+    L.hps_batch_stats.argtypes = [vp, ctypes.POINTER(ip)]
+    L.hps_batch_destroy.restype = i
+    L.hps_batch_destroy.argtypes = [vp]
+    L.hps_ctx_set_timing.restype = i
+    L.hps_ctx_set_timing.argtypes = [vp, i]
+    L.hps_ctx_phase_times.restype = i
+    L.hps_ctx_phase_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ip)]
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return load().hps_status_string(int(status)).decode()
+
+
+def _check(status: int, what: str, ok=(HPS_OK,)):
+    if status not in ok:
+        raise HpsError(status, what)
+    return status
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a tensor (None passes NULL)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _f64(t, name):
+    if t is not None and t.dtype != _torch().float64:
+        raise ValueError(f"{name} must be float64")
+    return t
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ---------------------------------------------------------------------------
+# C-ABI entry points, same names, tensors in place of pointers
+# ---------------------------------------------------------------------------
+
+def hps_ctx_create(stream=None) -> int:
+    """Context on the current device bound to `stream` (a torch stream, a raw
+    hipStream_t as int, or None for torch's current stream)."""
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    raw = stream if isinstance(stream, int) else stream.cuda_stream
+    out = ctypes.c_void_p()
+    _check(load().hps_ctx_create(ctypes.c_void_p(raw), ctypes.byref(out)), "hps_ctx_create")
+    return out.value
+
+
+def hps_ctx_destroy(ctx: int) -> None:
+    _check(load().hps_ctx_destroy(ctypes.c_void_p(ctx)), "hps_ctx_destroy")
+
+
+def hps_leaf_build(ctx: int, groups: Sequence[dict]) -> int:
+    """groups: dicts with p, box [nleaf,4] and optional a11, a22, c1, c2, k2b
+    [nleaf, p*p] (float64 device tensors)."""
+    arr = (hps_leaf_desc * len(groups))()
+    for k, g in enumerate(groups):
+        box = _f64(g["box"], "box")
+        arr[k].p = int(g["p"])
+        arr[k].nleaf = int(box.shape[0])
+        arr[k].box = _ptr(box)
+        for name in ("a11", "a12", "a22", "c1", "c2", "k2b"):
+            setattr(arr[k], name, _ptr(_f64(g.get(name), name)))
+    out = ctypes.c_void_p()
+    _check(load().hps_leaf_build(ctypes.c_void_p(ctx), arr, len(groups), ctypes.byref(out)),
+           "hps_leaf_build")
+    return out.value
+
+
+def hps_batch_nleaf(batch: int) -> int:
+    return load().hps_batch_nleaf(ctypes.c_void_p(batch))
+
+
+def hps_batch_group_dims(batch: int, g: int):
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(load().hps_batch_group_dims(ctypes.c_void_p(batch), g, *[ctypes.byref(x) for x in v]),
+           "hps_batch_group_dims")
+    return tuple(x.value for x in v)   # p, nleaf, ni, nb
+
+
+def hps_leaf_nodes(batch: int, g: int, xy) -> None:
+    _check(load().hps_leaf_nodes(ctypes.c_void_p(batch), g, _ptr(_f64(xy, "xy"))), "hps_leaf_nodes")
+
+
+def hps_leaf_operator(batch: int, g: int, Aii=None, Aib=None, Abi=None, Abb=None) -> None:
+    _check(load().hps_leaf_operator(ctypes.c_void_p(batch), g, _ptr(Aii), _ptr(Aib),
+                                    _ptr(Abi), _ptr(Abb)), "hps_leaf_operator")
+
+
+def hps_leaf_condense(batch: int, prec: int, tol: float, max_refine: int, f, S, w=None,
+                      info=None, flags: int = 0, allow=(HPS_OK,)) -> int:
+    st = load().hps_leaf_condense(ctypes.c_void_p(batch), int(prec), float(tol), int(max_refine),
+                                  _ptr(_f64(f, "f")), _ptr(_f64(S, "S")), _ptr(_f64(w, "w")),
+                                  _ptr(info), int(flags))
+    return _check(st, "hps_leaf_condense", allow)
+
+
+def hps_leaf_recover(batch: int, ub, f, ui, flags: int = 0) -> None:
+    _check(load().hps_leaf_recover(ctypes.c_void_p(batch), _ptr(_f64(ub, "ub")), _ptr(_f64(f, "f")),
+                                   _ptr(_f64(ui, "ui")), int(flags)), "hps_leaf_recover")
+
+
+def hps_batch_export(batch: int, Xt=None, h=None) -> None:
+    _check(load().hps_batch_export(ctypes.c_void_p(batch), _ptr(Xt), _ptr(h)), "hps_batch_export")
+
+
+def hps_batch_stats(batch: int) -> int:
+    v = ctypes.c_int()
+    _check(load().hps_batch_stats(ctypes.c_void_p(batch), ctypes.byref(v)), "hps_batch_stats")
+    return v.value
+
+
+def hps_batch_destroy(batch: int) -> None:
+    _check(load().hps_batch_destroy(ctypes.c_void_p(batch)), "hps_batch_destroy")
+
+
+def hps_ctx_set_timing(ctx: int, enable: bool) -> None:
+    _check(load().hps_ctx_set_timing(ctypes.c_void_p(ctx), 1 if enable else 0), "hps_ctx_set_timing")
+
+
+def hps_ctx_phase_times(ctx: int):
+    """{phase: (total ms, launches)} since the last call; synchronises."""
+    ms = (ctypes.c_double * HPS_NPHASE)()
+    n = (ctypes.c_int * HPS_NPHASE)()
+    _check(load().hps_ctx_phase_times(ctypes.c_void_p(ctx), ms, n), "hps_ctx_phase_times")
+    return {PHASES[k]: (ms[k], n[k]) for k in range(HPS_NPHASE)}

@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances.  FP64 path: normwise relative error <= 1e-10 for the operator
+blocks' neighbours X, h, S, w (the condition numbers of A_ii on these
+workloads stay below ~1e6, so c * kappa * eps_64 is below 1e-9 and the
+measured error is far smaller).  FP32 + FP64 refinement: <= 1e-9 relative on
+S and on the recovered u, the target the method is built for.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from _common import oracle_interior_f, oracle_leaf, relerr, sample_leaves
+from oracle import leaf as lf
+from oracle import interface as itf
+from paper_2211_14969_amd import hps, inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL_MIXED = 1e-9
+
+
+def _say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    if not T.cuda.is_available():
+        pytest.fail("no GPU visible")
+    hps.load()          # fails loudly if the library is missing
+    return T
+
+
+def _batch(problems):
+    from paper_2211_14969_amd.harness import LeafBatch
+    return LeafBatch(problems)
+
+
+def _small(p, nx=2, ny=2, kappa=None, kind="bump"):
+    if kind == "tiny":
+        return inputs.tiny(p=p, n=nx, kappa=kappa or 10.0)
+    if kind == "annulus":
+        return inputs.annulus(p=p, ntheta=nx, nr=ny, kappa=kappa or 12.0)
+    pr = inputs.multi_bump(p=p, n=nx, kappa=kappa or 3.0 * p, seed=3)
+    return pr
+
+
+# --------------------------------------------------------------------------
+# operator blocks
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("p,kind", [(4, "bump"), (8, "tiny"), (12, "annulus"), (16, "bump"),
+                                    (21, "annulus"), (32, "bump")])
+def test_operator_blocks(torch, p, kind):
+    prob = _small(p, 2, 2, kind=kind)
+    _say(f"operator p={p} {kind}")
+    B = _batch([prob])
+    ni, nb = (p - 2) ** 2, 4 * (p - 2)
+    L = prob.nleaf
+    mk = lambda *s: torch.empty(s, dtype=torch.float64, device="cuda")
+    Aii, Aib, Abi, Abb = mk(L, ni, ni), mk(L, ni, nb), mk(L, nb, ni), mk(L, nb, nb)
+    hps.hps_leaf_operator(B.batch, 0, Aii, Aib, Abi, Abb)
+    torch.cuda.synchronize()
+    for t in range(L):
+        bl, _ = oracle_leaf(prob, t)
+        for name, got in (("Aii", Aii), ("Aib", Aib), ("Abi", Abi), ("Abb", Abb)):
+            assert relerr(got[t].cpu().numpy(), getattr(bl, name)) < 1e-13, (name, t)
+    B.close()
+
+
+# --------------------------------------------------------------------------
+# condensation, FP64 and FP32 + refinement, across orders (ragged tiles)
+# --------------------------------------------------------------------------
+ORDERS = [4, 5, 6, 8, 12, 13, 16, 20, 24, 30, 32]
+
+
+def _check_condense(torch, prob, prec, tol, with_x=True, leaves=None, max_refine=3):
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=prec, max_refine=max_refine, sync=True)
+    assert st == hps.HPS_OK
+    Xt, h = B.export()
+    torch.cuda.synchronize()
+    nb, ni = 4 * (prob.p - 2), (prob.p - 2) ** 2
+    S = S.view(prob.nleaf, nb, nb).cpu().numpy()
+    Xt = Xt.view(prob.nleaf, nb, ni).cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    worst = {"S": 0.0, "X": 0.0}
+    for t in (leaves if leaves is not None else range(prob.nleaf)):
+        _, c = oracle_leaf(prob, t)
+        eS, eX = relerr(S[t], c.S), relerr(Xt[t].T, c.X)
+        worst["S"] = max(worst["S"], eS)
+        worst["X"] = max(worst["X"], eX)
+    _say(f"  {prob.name} prec={prec} worst {worst}")
+    assert worst["S"] <= tol
+    if with_x:
+        assert worst["X"] <= (tol if prec == hps.HPS_FP64 else 1e-8)
+    B.close()
+    return worst
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_condense_fp64_orders(torch, p):
+    _say(f"condense fp64 p={p}")
+    _check_condense(torch, _small(p, 2, 3), hps.HPS_FP64, TOL64)
+
+
+@pytest.mark.parametrize("p", ORDERS)
+def test_condense_fp32_refine_orders(torch, p):
+    _say(f"condense fp32+refine p={p}")
+    _check_condense(torch, _small(p, 3, 2), hps.HPS_FP32_REFINE, TOL_MIXED)
+
+
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+def test_annulus_variable_coefficients(torch, prec):
+    _say(f"annulus prec={prec}")
+    _check_condense(torch, inputs.annulus(p=20, ntheta=4, nr=2, kappa=150.0), prec,
+                    TOL64 if prec == hps.HPS_FP64 else TOL_MIXED)
+
+
+def test_single_leaf(torch):
+    _say("single leaf p=16")
+    _check_condense(torch, _small(16, 1, 1), hps.HPS_FP64, TOL64)
+
+
+# --------------------------------------------------------------------------
+# body load f: h and w
+# --------------------------------------------------------------------------
+def _forced_problem(p, nx=2, ny=2):
+    kappa = 6.0
+    u = lambda x, y, xp: xp.sin(3 * x) * xp.cos(2 * y) + x * y
+    f = lambda x, y, xp: (13.0 - kappa ** 2) * xp.sin(3 * x) * xp.cos(2 * y) - kappa ** 2 * x * y
+    return inputs.Problem(name=f"forced_p{p}", nx=nx, ny=ny, p=p, kappa=kappa,
+                          coef={"k2b": lambda x, y, xp: xp.zeros_like(x) + kappa ** 2},
+                          g=u, exact=u, f=f)
+
+
+@pytest.mark.parametrize("prec,p", [(hps.HPS_FP64, 10), (hps.HPS_FP64, 17),
+                                    (hps.HPS_FP32_REFINE, 10), (hps.HPS_FP32_REFINE, 17)])
+def test_condense_with_body_load(torch, prec, p):
+    _say(f"forced prec={prec} p={p}")
+    prob = _forced_problem(p)
+    B = _batch([prob])
+    f = B.interior_f()
+    S, w, info, st = B.condense(prec=prec, f=f, max_refine=3, sync=True)
+    Xt, h = B.export()
+    nb, ni = 4 * (p - 2), (p - 2) ** 2
+    S, w, h = (S.view(-1, nb, nb).cpu().numpy(), w.view(-1, nb).cpu().numpy(),
+               h.view(-1, ni).cpu().numpy())
+    tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+    for t in range(prob.nleaf):
+        _, c = oracle_leaf(prob, t, oracle_interior_f(prob, t))
+        assert relerr(S[t], c.S) <= tol
+        assert relerr(h[t], c.h) <= tol
+        assert relerr(w[t], c.w) <= tol
+    B.close()
+
+
+# --------------------------------------------------------------------------
+# recovery: stored X and the re-factor mode, fed the oracle's u_b
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+def test_recover_with_oracle_boundary_values(torch, prec):
+    prob = inputs.tiny()
+    _say(f"recover tiny prec={prec}")
+    sol = itf.solve(prob)
+    ub = np.stack([sol.uedge[sol.num.slot[t]] for t in range(prob.nleaf)])
+    B = _batch([prob])
+    B.condense(prec=prec, max_refine=3, sync=True)
+    ub_d = torch.as_tensor(ub.ravel(), device="cuda")
+    ui = B.recover(ub_d, sync=True).view(prob.nleaf, -1).cpu().numpy()
+    ui_rf = B.recover(ub_d, refactor=True, sync=True).view(prob.nleaf, -1).cpu().numpy()
+    tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+    assert relerr(ui, sol.uint) <= tol
+    assert relerr(ui_rf, sol.uint) <= TOL64
+    B.close()
+
+
+def test_recover_refactor_with_body_load(torch):
+    prob = _forced_problem(12, 3, 2)
+    _say("recover refactor forced")
+    leaves = itf.build_leaves(prob)
+    sol = itf.solve(prob, leaves)
+    ub = np.stack([sol.uedge[sol.num.slot[t]] for t in range(prob.nleaf)])
+    B = _batch([prob])
+    f = B.interior_f()
+    ui = B.recover(torch.as_tensor(ub.ravel(), device="cuda"), f=f, refactor=True, sync=True)
+    assert relerr(ui.view(prob.nleaf, -1).cpu().numpy(), sol.uint) <= TOL64
+    B.close()
+
+
+# --------------------------------------------------------------------------
+# end to end on the tiny workload: GPU condense -> host interface solve ->
+# GPU recover, against the exact solution and the oracle's solution
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+def test_end_to_end_tiny(torch, prec):
+    from paper_2211_14969_amd.harness import interface_solve
+    prob = inputs.tiny()
+    _say(f"end-to-end tiny prec={prec}")
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=prec, max_refine=3, sync=True)
+    nb = 4 * (prob.p - 2)
+    Bidx = lf.flat(prob.p, lf.boundary_nodes(prob.p))
+    xy_b = B.groups[0].xy[:, Bidx, :].cpu().numpy()
+    ub = interface_solve(prob, S.view(-1, nb, nb).cpu().numpy(), w.view(-1, nb).cpu().numpy(), xy_b)
+    ui = B.recover(torch.as_tensor(ub.ravel(), device="cuda"), sync=True)
+    ui = ui.view(prob.nleaf, -1).cpu().numpy()
+    sol = itf.solve(prob)
+    ub_o = np.stack([sol.uedge[sol.num.slot[t]] for t in range(prob.nleaf)])
+    assert relerr(ui, sol.uint) <= 1e-9
+    assert relerr(ub, ub_o) <= 1e-9
+    # exact solution sin(kappa x1) at the interior nodes
+    I = lf.flat(prob.p, lf.interior_nodes(prob.p))
+    xy_i = B.groups[0].xy[:, I, :].cpu().numpy()
+    exact = np.sin(prob.kappa * xy_i[..., 0])
+    assert relerr(ui, exact) < 1e-3
+    B.close()
+
+
+# --------------------------------------------------------------------------
+# failure reporting
+# --------------------------------------------------------------------------
+def test_singular_leaf_reports_zero_pivot(torch):
+    zero = lambda x, y, xp: xp.zeros_like(x)
+    prob = inputs.Problem(name="zero", nx=2, ny=1, p=8, kappa=0.0,
+                          coef={"a11": zero, "a22": zero, "k2b": zero})
+    _say("singular")
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=hps.HPS_FP64, sync=True, allow=(hps.HPS_ERR_SINGULAR,))
+    assert st == hps.HPS_ERR_SINGULAR
+    assert np.all(info.cpu().numpy() == 1)
+    B.close()
+
+
+def test_nonfinite_coefficient_is_flagged(torch):
+    prob = inputs.tiny(p=8, n=2)
+    # NaN in the interior of the leaves right of x1 = 0.5 (leaves 1 and 3)
+    prob.coef["k2b"] = lambda x, y, xp: xp.where(x > 0.5, xp.zeros_like(x) + float("nan"),
+                                                  xp.zeros_like(x) + 100.0)
+    _say("nonfinite")
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=hps.HPS_FP64, sync=True,
+                                allow=(hps.HPS_ERR_NONFINITE, hps.HPS_ERR_SINGULAR))
+    assert st in (hps.HPS_ERR_NONFINITE, hps.HPS_ERR_SINGULAR)
+    inf = info.cpu().numpy()
+    assert inf[0] == 0 and inf[2] == 0 and inf[1] != 0 and inf[3] != 0
+    B.close()
+
+
+def test_refinement_not_converged_flag(torch):
+    prob = _small(12, 2, 2)
+    _say("not converged")
+    B = _batch([prob])
+    st = hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 1e-300, 1, None,
+                               *B.alloc_outputs(), hps.HPS_SYNC,
+                               allow=(hps.HPS_ERR_NOT_CONVERGED,))
+    assert st == hps.HPS_ERR_NOT_CONVERGED
+    B.close()
+
+
+def test_invalid_arguments_enqueue_nothing(torch):
+    prob = _small(8, 1, 1)
+    B = _batch([prob])
+    S, w, info = B.alloc_outputs()
+    with pytest.raises(hps.HpsError):
+        hps.hps_leaf_condense(B.batch, 7, 0.0, 1, None, S, w, info)
+    with pytest.raises(hps.HpsError):
+        hps.hps_leaf_condense(B.batch, hps.HPS_FP64, 0.0, 99, None, S, w, info)
+    with pytest.raises(hps.HpsError):
+        hps.hps_leaf_recover(B.batch, S, None, S)    # recover before any condense
+    box = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
+    for bad in ({"p": 3, "box": box}, {"p": 33, "box": box},
+                {"p": 8, "box": box, "a12": torch.zeros((1, 64), dtype=torch.float64, device="cuda")}):
+        with pytest.raises(hps.HpsError):
+            hps.hps_leaf_build(B.ctx, [bad])
+    B.close()
