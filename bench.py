@@ -78,6 +78,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32+refinement comparison run")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB three times "
+                         "(calibrates the HBM traffic counters against a known byte count)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -93,6 +96,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("no ROCm device visible", file=sys.stderr)
         return 1
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_mib, "copies": 3}))
+        return 0
     hps.load()
     prob = inputs.single_bump()
     p, L = prob.p, prob.nleaf

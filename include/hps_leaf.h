@@ -54,7 +54,7 @@ typedef enum {
   HPS_ERR_OOM = -2,           /* device allocation failed                      */
   HPS_ERR_HIP = -3,           /* a HIP runtime call failed                     */
   HPS_ERR_SINGULAR = -4,      /* (HPS_SYNC) some leaf had an exactly zero pivot */
-  HPS_ERR_NOT_CONVERGED = -5, /* (HPS_SYNC) refinement did not reach `tol`     */
+  HPS_ERR_NOT_CONVERGED = -5, /* reserved (refinement failures fall back to FP64) */
   HPS_ERR_NONFINITE = -6      /* (HPS_SYNC) a leaf produced Inf or NaN         */
 } hps_status;
 
@@ -127,21 +127,24 @@ hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib,
  * partial pivoting, computes X (and h when f != NULL), refines X in FP64
  * when prec == HPS_FP32_REFINE, and forms S and w in FP64.
  *   prec       : HPS_FP64 or HPS_FP32_REFINE
- *   tol        : refinement stop test on the normwise backward error of the
- *                FP64 residual r = A_ib - A_ii X (per leaf):
- *                ||r||_F / (||A_ii||_F ||X||_F + ||[A_ib f_i]||_F) <= tol.
- *                Ignored for HPS_FP64.  <= 0 selects ni * 2^-53.
- *   max_refine : FP32 correction steps at most (HPS_FP32_REFINE), 0..16.
- *                The residual is evaluated before each correction and once
- *                more after the last one; a leaf stops as soon as it passes,
- *                and is flagged -1 if it never does.
+ *   tol        : refinement target (HPS_FP32_REFINE; ignored for HPS_FP64):
+ *                a leaf stops refining when the estimated relative forward
+ *                error of X, (||r_k|| / ||r_{k-1}||) ||dX_k|| / ||X_k|| from
+ *                the FP64 residuals r = A_ib - A_ii X, is at most tol, or
+ *                when its normwise backward error
+ *                ||r|| / (||A_ii|| ||X|| + ||[A_ib f_i]||) is at FP64
+ *                rounding level.  <= 0 selects 1e-10.
+ *   max_refine : FP32 correction steps at most, 0..16.  The residual is
+ *                evaluated before each correction and once more after the
+ *                last.  Leaves that never pass (A_ii too ill-conditioned for
+ *                an FP32 factorisation, e.g. near a leaf resonance) are
+ *                condensed again in FP64, so every leaf ends accurate.
  *   f          : device [total leaves][ni] interior body load, or NULL (f = 0)
  *   S          : device [total leaves][nb][nb]   (output)
  *   w          : device [total leaves][nb] or NULL (output; 0 when f == NULL)
  *   info       : device [total leaves] or NULL (output):
  *                0 ok; k > 0 exact zero pivot in column k (1-based, LAPACK
- *                getrf convention); -1 refinement did not meet tol;
- *                -2 non-finite value in X or S.
+ *                getrf convention); -2 non-finite value in X or S.
  *   flags      : HPS_SYNC or 0
  * The stored X and h are kept in the batch for hps_leaf_recover.  Async
  * unless HPS_SYNC. */
@@ -168,9 +171,11 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
  * Either may be NULL.  Async. */
 hps_status hps_batch_export(hps_batch *b, double *Xt, double *h);
 
-/* Refinement statistics of the last hps_leaf_condense (host pointer args):
- * number of refinement steps executed. */
-hps_status hps_batch_stats(const hps_batch *b, int *refine_steps);
+/* Statistics of the last hps_leaf_condense (host pointers, either may be
+ * NULL): the refinement step limit it ran with, and the number of leaves the
+ * FP32 + refinement path handed to the FP64 fallback.  Reading fp64_redo
+ * synchronises the context stream. */
+hps_status hps_batch_stats(const hps_batch *b, int *refine_steps, int *fp64_redo);
 
 /* Per-phase timing with HIP events on the context stream (tracing aid).
  * While enabled, every kernel launch of hps_leaf_condense / hps_leaf_recover

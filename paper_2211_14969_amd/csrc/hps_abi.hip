@@ -99,7 +99,10 @@ struct hps_batch {
   bool have_x = false;
   int *info = nullptr;      // [nleaf] internal per-leaf status
   int *conv = nullptr;      // [nleaf] refinement converged flags
-  double *norms = nullptr;  // [nleaf][4] refinement norms
+  double *norms = nullptr;  // [nleaf][8] refinement norms
+  int *list = nullptr;      // [nleaf] leaves to redo in FP64
+  int *count = nullptr;     // [2] length of list; leaves redone in FP64 by
+                            //     the last condense
   void *ws = nullptr;       // LU work matrices of the leaves in flight
   size_t ws_bytes = 0;
   int *piv = nullptr, *rstep = nullptr;
@@ -287,6 +290,8 @@ hps_status hps_batch_destroy(hps_batch *b) {
   fr(b->info);
   fr(b->conv);
   fr(b->norms);
+  fr(b->list);
+  fr(b->count);
   fr(b->ws);
   fr(b->piv);
   fr(b->rstep);
@@ -348,7 +353,9 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
         hipMalloc(&b->h, sizeof(double) * b->h_total) != hipSuccess ||
         hipMalloc(&b->info, sizeof(int) * b->nleaf) != hipSuccess ||
         hipMalloc(&b->conv, sizeof(int) * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->norms, sizeof(double) * 4 * b->nleaf) != hipSuccess)
+        hipMalloc(&b->norms, sizeof(double) * 8 * b->nleaf) != hipSuccess ||
+        hipMalloc(&b->list, sizeof(int) * b->nleaf) != hipSuccess ||
+        hipMalloc(&b->count, 2 * sizeof(int)) != hipSuccess)
       st = HPS_ERR_OOM;
   }
   if (st != HPS_OK) {
@@ -402,6 +409,7 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
   if (st != HPS_OK) return st;
   hipStream_t s = b->ctx->stream;
   const int nref = fp32 ? max_refine : 0;
+  HPS_TRY(hps::launch_fill_int(b->count, 2, 0, s));
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     const Group &G = b->groups[gi];
     const hps::Geom g0 = make_geom(G.d, G.dtab, G.geom.nb + extra);
@@ -419,24 +427,26 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
       o.Xt = Xt;
       o.h = hh;
       o.ui = nullptr;
+      o.norms = nullptr;
       o.skip = nullptr;
       o.mode = hps::BACK_STORE;
       HPS_TRY(timed(b->ctx, 2, [&] { return hps::launch_backsolve(g, n, fp32, b->ws, b->piv, b->rstep, o, s); }));
       if (fp32) {
         // FP64 iterative refinement: residual -> stop test -> FP32 correction,
-        // then one more residual after the last correction for the final test.
+        // and one more residual after the last correction for the final test.
         int *conv = b->conv + gl;
-        double *nrm = b->norms + 4 * (size_t)gl;
-        const double tl = tol > 0.0 ? tol : (double)g.ni * 0x1p-53;
+        double *nrm = b->norms + 8 * (size_t)gl;
+        const double tl = tol > 0.0 ? tol : 1e-10;
         HPS_TRY(hps::launch_fill_int(conv, n, 0, s));
         o.mode = hps::BACK_ACCUM;
         o.skip = conv;
+        o.norms = nrm;
         for (int it = 0; it <= nref; ++it) {
           HPS_TRY(timed(b->ctx, 3, [&] {
             return hps::launch_residual(g, n, (float *)b->ws, Xt, hh, fc, conv, nrm, s);
           }));
           HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_convcheck(n, nrm, tl, conv, inf, it == nref ? 1 : 0, s);
+            return hps::launch_convcheck(n, nrm, tl, conv, inf, it, it == nref ? 1 : 0, s);
           }));
           if (it == nref) break;
           HPS_TRY(timed(b->ctx, 3, [&] {
@@ -444,6 +454,36 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
           }));
           HPS_TRY(timed(b->ctx, 3, [&] {
             return hps::launch_backsolve(g, n, true, b->ws, b->piv, b->rstep, o, s);
+          }));
+        }
+        // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
+        // for an FP32 factorisation, e.g. near a leaf resonance) are condensed
+        // again in FP64, reusing the FP32 workspace, in passes of `cap` leaves.
+        HPS_TRY(hps::launch_fill_int(b->count, 1, 0, s));
+        HPS_TRY(timed(b->ctx, 3, [&] { return hps::launch_collect(n, inf, b->list, b->count, b->count + 1, s); }));
+        const size_t per64 = work_bytes_per_leaf(g, false);
+        const int cap = (int)std::max<size_t>(1, std::min<size_t>(b->ws_bytes / per64, n));
+        hps::BackOut o64;
+        o64.Xt = Xt;
+        o64.h = hh;
+        o64.ui = nullptr;
+        o64.norms = nullptr;
+        o64.skip = nullptr;
+        o64.mode = hps::BACK_STORE;
+        for (int s0 = 0; s0 < n; s0 += cap) {
+          hps::Sel sel;
+          sel.list = b->list;
+          sel.count = b->count;
+          sel.slot0 = s0;
+          const int nb_ = std::min(cap, n - s0);
+          HPS_TRY(timed(b->ctx, 3, [&] {
+            return hps::launch_build(g, nb_, hps::RHS_CONDENSE, false, b->ws, fc, nullptr, s, sel);
+          }));
+          HPS_TRY(timed(b->ctx, 3, [&] {
+            return hps::launch_factor(g, nb_, false, b->ws, b->piv, b->rstep, inf, s, sel);
+          }));
+          HPS_TRY(timed(b->ctx, 3, [&] {
+            return hps::launch_backsolve(g, nb_, false, b->ws, b->piv, b->rstep, o64, s, sel);
           }));
         }
       }
@@ -489,6 +529,7 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
         o.Xt = nullptr;
         o.h = nullptr;
         o.ui = ui + G.h_off + (size_t)l0 * g.ni;
+        o.norms = nullptr;
         o.skip = nullptr;
         o.mode = hps::BACK_UI;
         HPS_TRY(timed(b->ctx, 5, [&] {
@@ -525,9 +566,15 @@ hps_status hps_batch_export(hps_batch *b, double *Xt, double *h) {
   return HPS_OK;
 }
 
-hps_status hps_batch_stats(const hps_batch *b, int *refine_steps) {
-  if (!b || !refine_steps) return HPS_ERR_INVALID;
-  *refine_steps = b->last_refine;
+hps_status hps_batch_stats(const hps_batch *b, int *refine_steps, int *fp64_redo) {
+  if (!b) return HPS_ERR_INVALID;
+  if (refine_steps) *refine_steps = b->last_refine;
+  if (fp64_redo) {
+    int v[2] = {0, 0};
+    HPS_TRY(hipStreamSynchronize(b->ctx->stream));
+    HPS_TRY(hipMemcpy(v, b->count, sizeof(v), hipMemcpyDeviceToHost));
+    *fp64_redo = v[1];
+  }
   return HPS_OK;
 }
 

@@ -36,10 +36,19 @@ enum BackMode : int {
   BACK_UI = 2        // single column -> ui
 };
 
+// Leaf selection of a launch: block b uses work-matrix slot b and, when
+// `list` is set, leaf list[slot0 + b]; blocks at or past *count exit at once.
+struct Sel {
+  const int *list = nullptr;
+  const int *count = nullptr;
+  int slot0 = 0;
+};
+
 struct BackOut {
   double *Xt;        // [nleaf][nb][ni]
   double *h;         // [nleaf][ni]   (nullptr when no f column)
   double *ui;        // [nleaf][ni]   (BACK_UI)
+  double *norms;     // [nleaf][8]: slot 5 receives ||dX||^2 (BACK_ACCUM)
   const int *skip;   // [nleaf] leaves to leave untouched (nullptr = none)
   int mode;
 };
@@ -48,20 +57,23 @@ constexpr int kInfoActive = 0x7fffffff;
 
 // Launchers (hps_kernels.hip).  All enqueue on `s` and return hipError_t.
 hipError_t launch_build(const Geom &g, int nleaf, int mode, bool fp32, void *M,
-                        const double *f, const double *ub, hipStream_t s);
+                        const double *f, const double *ub, hipStream_t s,
+                        const Sel &sel = Sel());
 hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
-                         int *rstep, int *info, hipStream_t s);
+                         int *rstep, int *info, hipStream_t s, const Sel &sel = Sel());
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
                             const int *piv, const int *rstep, const BackOut &o,
-                            hipStream_t s);
+                            hipStream_t s, const Sel &sel = Sel());
 hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M,
                            const int *piv, const int *rstep, const int *skip,
                            hipStream_t s);
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip,
                            double *norms, hipStream_t s);
-hipError_t launch_convcheck(int nleaf, const double *norms, double tol, int *conv,
-                            int *info, int last, hipStream_t s);
+hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
+                            int it, int last, hipStream_t s);
+hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total,
+                          hipStream_t s);
 hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h,
                         double *S, double *w, int *info, hipStream_t s);
 hipError_t launch_recover(const Geom &g, int nleaf, const double *Xt, const double *h,

@@ -87,6 +87,16 @@ __device__ __forceinline__ size_t tix(int r, int c, int CT) {
   return ((size_t)((r >> 4) * CT + (c >> 4)) << 8) + Tile<T>::inner(r, c);
 }
 
+// Leaf handled by this block (false: the block has nothing to do).
+__device__ __forceinline__ bool resolve_leaf(const Sel &sel, int &leaf) {
+  leaf = blockIdx.x;
+  if (!sel.list) return true;
+  const int slot = sel.slot0 + (int)blockIdx.x;
+  if (slot >= *sel.count) return false;
+  leaf = sel.list[slot];
+  return true;
+}
+
 __device__ __forceinline__ size_t leaf_stride(const Geom &g) {
   return (size_t)g.RT * g.CT * 256;
 }
@@ -149,15 +159,16 @@ __device__ __forceinline__ void stage_tables(const Geom &g, double *sD, double *
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_build(Geom g, int mode, T *M, const double *f,
-                                               const double *ub) {
+                                               const double *ub, Sel sel) {
   __shared__ double sD[32 * 32], sD2[32 * 32];
-  const int leaf = blockIdx.x;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
   stage_tables(g, sD, sD2);
   __syncthreads();
   const LeafScale sc = leaf_scale(g, leaf);
   const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R, CT = g.CT;
   const size_t nbase = (size_t)leaf * p * p;
-  T *Ml = M + leaf_stride(g) * leaf;
+  T *Ml = M + leaf_stride(g) * blockIdx.x;
   const size_t total = leaf_stride(g);
   for (size_t e = threadIdx.x; e < total; e += blockDim.x) {
     const int tile = (int)(e >> 8);
@@ -209,10 +220,12 @@ __device__ __forceinline__ T abs_key(T v) {
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rstep,
-                                               int *info, int CH) {
+                                               int *info, int CH, Sel sel) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int leaf = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
   const int R = g.R, RT = g.RT, CT = g.CT;
   const int UST = CH + 16;
   T *P = (T *)smem;                       // [R][kPST]   panel
@@ -223,7 +236,7 @@ __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rste
   int *pv = tileAct + RT;                 // [16]
   int *redi = pv + 16;                    // [NW]
   int *zeroPiv = redi + NW;               // [1]
-  T *Ml = M + leaf_stride(g) * leaf;
+  T *Ml = M + leaf_stride(g) * wi;
 
   for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
   if (tid == 0) *zeroPiv = 0;
@@ -334,10 +347,10 @@ __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rste
       const int r = e >> 4, c = e & 15;
       Ml[tix<T>(r, k * 16 + c, CT)] = P[r * kPST + c];
     }
-    if (tid < 16) piv[(size_t)leaf * R + k * 16 + tid] = pv[tid];
+    if (tid < 16) piv[(size_t)wi * R + k * 16 + tid] = pv[tid];
     __syncthreads();
   }
-  for (int r = tid; r < R; r += NT) rstep[(size_t)leaf * R + r] = rst[r];
+  for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
   if (tid == 0) info[leaf] = *zeroPiv;
 }
 
@@ -418,22 +431,26 @@ __global__ void __launch_bounds__(NT) k_fwdsolve(Geom g, T *M, const int *piv,
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
-                                                  const int *rstep, BackOut o) {
+                                                  const int *rstep, BackOut o, Sel sel) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int leaf = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
   if (o.skip && o.skip[leaf]) return;
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb;
   const int NRC = CT * 16 - R, YST = NRC + 16;
-  T *Y = (T *)smem;                 // [16][YST]
+  double *red = (double *)smem;     // [NW]
+  T *Y = (T *)(red + NW);           // [16][YST]
   T *Ut = Y + 16 * YST;             // [16][kPST]
   int *rst = (int *)(Ut + 16 * kPST);
   int *tileAny = rst + R;
   int *pv = tileAny + RT;
-  T *Ml = M + leaf_stride(g) * leaf;
-  for (int r = tid; r < R; r += NT) rst[r] = rstep[(size_t)leaf * R + r];
+  T *Ml = M + leaf_stride(g) * wi;
+  double nd = 0.0;
+  for (int r = tid; r < R; r += NT) rst[r] = rstep[(size_t)wi * R + r];
   for (int k = RT - 1; k >= 0; --k) {
-    if (tid < 16) pv[tid] = piv[(size_t)leaf * R + k * 16 + tid];
+    if (tid < 16) pv[tid] = piv[(size_t)wi * R + k * 16 + tid];
     __syncthreads();
     for (int e = tid; e < 256; e += NT) {
       const int s = e >> 4, q = e & 15;
@@ -471,8 +488,12 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
           } else {
             double *dst = (jr < nb) ? o.Xt + ((size_t)leaf * nb + jr) * ni + i
                                     : o.h + (size_t)leaf * ni + i;
-            if (o.mode == BACK_STORE) *dst = v;
-            else *dst += v;
+            if (o.mode == BACK_STORE) {
+              *dst = v;
+            } else {
+              *dst += v;
+              nd += v * v;
+            }
           }
         }
       }
@@ -499,6 +520,17 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
         for (int q = 0; q < 4; ++q) Ct[q * 64 + lane] = acc[q];
       }
       __syncthreads();
+    }
+  }
+  if (o.mode == BACK_ACCUM) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
+    if (lane == 0) red[wv] = nd;
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0;
+      for (int w = 0; w < NW; ++w) a += red[w];
+      o.norms[8 * (size_t)leaf + 5] = a;
     }
   }
 }
@@ -595,24 +627,46 @@ __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const doub
   if (threadIdx.x < 4) {
     double a = 0.0;
     for (int w = 0; w < 4; ++w) a += red[w][threadIdx.x];
-    norms[4 * (size_t)leaf + threadIdx.x] = a;
+    norms[8 * (size_t)leaf + threadIdx.x] = a;
   }
 }
 
-// Stop test of the refinement: normwise backward error
-//   eta = ||r||_F / (||A_ii||_F ||X||_F + ||[A_ib f]||_F) <= tol.
-// On the final check a leaf that has not met it is flagged -1.
-__global__ void k_convcheck(int nleaf, const double *norms, double tol, int *conv,
-                            int *info, int last) {
+// Stop test of the refinement, per leaf, after the residual r_k of X_k:
+//  * the normwise backward error ||r||/(||A_ii|| ||X|| + ||[A_ib f]||) is at
+//    the FP64 rounding level, or
+//  * the estimated forward error (||r_k|| / ||r_{k-1}||) ||dX_k||, i.e. the
+//    observed contraction of the residual times the last correction, is at
+//    most tol ||X_k||.
+// On the final check a leaf that passed neither is flagged -1.
+// norms[8l + ...]: 0 ||r||^2, 1 ||X||^2, 2 ||A_ii||^2, 3 ||[A_ib f]||^2,
+// 4 previous ||r||^2, 5 ||dX||^2 of the last correction.
+__global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
+                            int it, int last) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaf || conv[l]) return;
-  const double *n = norms + 4 * (size_t)l;
+  double *n = norms + 8 * (size_t)l;
   const double eta = sqrt(n[0]) / (sqrt(n[2]) * sqrt(n[1]) + sqrt(n[3]));
-  if (eta <= tol) {
+  bool ok = eta <= 4.0 * 0x1p-53;
+  if (!ok && it > 0 && n[4] > 0.0) {
+    const double est = sqrt(n[0] / n[4]) * sqrt(n[5]);
+    ok = est <= tol * sqrt(n[1]);
+  }
+  n[4] = n[0];
+  if (ok) {
     conv[l] = 1;
   } else if (last && info[l] == 0) {
     info[l] = -1;
   }
+}
+
+// Leaves whose refinement failed (info -1) are listed for an FP64 redo.
+__global__ void k_collect(int nleaf, int *info, int *list, int *count, int *total) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nleaf || info[l] != -1) return;
+  atomicAdd(total, 1);
+  const int slot = atomicAdd(count, 1);
+  list[slot] = l;
+  info[l] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -804,7 +858,8 @@ int pick_ch(const Geom &g) {
 template <typename T>
 size_t solve_lds(const Geom &g) {
   const int NRC = g.CT * 16 - g.R;
-  size_t b = sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST);
+  size_t b = sizeof(double) * (kSolveNT / 64);
+  b += sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST);
   b += sizeof(int) * ((size_t)g.R + g.RT + 16);
   return b;
 }
@@ -827,16 +882,18 @@ size_t factor_lds_bytes(const Geom &g, bool fp32) {
 }
 
 hipError_t launch_build(const Geom &g, int nleaf, int mode, bool fp32, void *M,
-                        const double *f, const double *ub, hipStream_t s) {
+                        const double *f, const double *ub, hipStream_t s, const Sel &sel) {
   if (fp32)
-    hipLaunchKernelGGL(k_build<float>, dim3(nleaf), dim3(256), 0, s, g, mode, (float *)M, f, ub);
+    hipLaunchKernelGGL(k_build<float>, dim3(nleaf), dim3(256), 0, s, g, mode, (float *)M, f, ub,
+                       sel);
   else
-    hipLaunchKernelGGL(k_build<double>, dim3(nleaf), dim3(256), 0, s, g, mode, (double *)M, f, ub);
+    hipLaunchKernelGGL(k_build<double>, dim3(nleaf), dim3(256), 0, s, g, mode, (double *)M, f, ub,
+                       sel);
   return hipGetLastError();
 }
 
 hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv, int *rstep,
-                         int *info, hipStream_t s) {
+                         int *info, hipStream_t s, const Sel &sel) {
   if (fp32) {
     const int ch = pick_ch<float>(g);
     if (!ch) return hipErrorInvalidValue;
@@ -844,7 +901,7 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
     hipError_t e = set_lds(k_factor<float, kFactorNT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_factor<float, kFactorNT>), dim3(nleaf), dim3(kFactorNT), lds, s, g,
-                       (float *)M, piv, rstep, info, ch);
+                       (float *)M, piv, rstep, info, ch, sel);
   } else {
     const int ch = pick_ch<double>(g);
     if (!ch) return hipErrorInvalidValue;
@@ -852,25 +909,25 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
     hipError_t e = set_lds(k_factor<double, kFactorNT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_factor<double, kFactorNT>), dim3(nleaf), dim3(kFactorNT), lds, s, g,
-                       (double *)M, piv, rstep, info, ch);
+                       (double *)M, piv, rstep, info, ch, sel);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
-                            const int *rstep, const BackOut &o, hipStream_t s) {
+                            const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
   if (fp32) {
     const size_t lds = solve_lds<float>(g);
     hipError_t e = set_lds(k_backsolve<float, kSolveNT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_backsolve<float, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (float *)M, piv, rstep, o);
+                       (float *)M, piv, rstep, o, sel);
   } else {
     const size_t lds = solve_lds<double>(g);
     hipError_t e = set_lds(k_backsolve<double, kSolveNT>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_backsolve<double, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (double *)M, piv, rstep, o);
+                       (double *)M, piv, rstep, o, sel);
   }
   return hipGetLastError();
 }
@@ -900,10 +957,17 @@ hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *X
   return hipGetLastError();
 }
 
-hipError_t launch_convcheck(int nleaf, const double *norms, double tol, int *conv, int *info,
+hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info, int it,
                             int last, hipStream_t s) {
   hipLaunchKernelGGL(k_convcheck, dim3((nleaf + 255) / 256), dim3(256), 0, s, nleaf, norms, tol,
-                     conv, info, last);
+                     conv, info, it, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_collect, dim3((nleaf + 255) / 256), dim3(256), 0, s, nleaf, info, list,
+                     count, total);
   return hipGetLastError();
 }
 

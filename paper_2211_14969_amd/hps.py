@@ -98,7 +98,7 @@ def load(path: str = LIB_PATH):
     L.hps_batch_export.restype = i
     L.hps_batch_export.argtypes = [vp, vp, vp]
     L.hps_batch_stats.restype = i
-    L.hps_batch_stats.argtypes = [vp, ctypes.POINTER(ip)]
+    L.hps_batch_stats.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip)]
     L.hps_batch_destroy.restype = i
     L.hps_batch_destroy.argtypes = [vp]
     L.hps_ctx_set_timing.restype = i
@@ -215,10 +215,12 @@ def hps_batch_export(batch: int, Xt=None, h=None) -> None:
     _check(load().hps_batch_export(ctypes.c_void_p(batch), _ptr(Xt), _ptr(h)), "hps_batch_export")
 
 
-def hps_batch_stats(batch: int) -> int:
-    v = ctypes.c_int()
-    _check(load().hps_batch_stats(ctypes.c_void_p(batch), ctypes.byref(v)), "hps_batch_stats")
-    return v.value
+def hps_batch_stats(batch: int):
+    """(refinement step limit, leaves redone in FP64) of the last condense."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(load().hps_batch_stats(ctypes.c_void_p(batch), ctypes.byref(a), ctypes.byref(b)),
+           "hps_batch_stats")
+    return a.value, b.value
 
 
 def hps_batch_destroy(batch: int) -> None:

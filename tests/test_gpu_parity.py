@@ -251,14 +251,33 @@ def test_nonfinite_coefficient_is_flagged(torch):
     B.close()
 
 
-def test_refinement_not_converged_flag(torch):
+def test_fp64_fallback_when_refinement_cannot_meet_tol(torch):
+    """An unreachable refinement target sends every leaf to the FP64 redo;
+    the results are then FP64-accurate and the redo count is reported."""
     prob = _small(12, 2, 2)
-    _say("not converged")
+    _say("fallback")
     B = _batch([prob])
-    st = hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 1e-300, 1, None,
-                               *B.alloc_outputs(), hps.HPS_SYNC,
-                               allow=(hps.HPS_ERR_NOT_CONVERGED,))
-    assert st == hps.HPS_ERR_NOT_CONVERGED
+    S, w, info = B.alloc_outputs()
+    st = hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 1e-300, 1, None, S, w, info,
+                               hps.HPS_SYNC)
+    assert st == hps.HPS_OK
+    assert hps.hps_batch_stats(B.batch) == (1, prob.nleaf)
+    assert np.all(info.cpu().numpy() == 0)
+    nb = 4 * (prob.p - 2)
+    Sg = S.view(-1, nb, nb).cpu().numpy()
+    for t in range(prob.nleaf):
+        _, c = oracle_leaf(prob, t)
+        assert relerr(Sg[t], c.S) <= TOL64
+    B.close()
+
+
+def test_refinement_stats_typical_leaves(torch):
+    """Well-conditioned leaves (the annulus workload's) meet the default
+    target without the FP64 redo."""
+    prob = inputs.annulus(p=20, ntheta=8, nr=2, kappa=150.0)
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=hps.HPS_FP32_REFINE, max_refine=2, sync=True)
+    assert hps.hps_batch_stats(B.batch) == (2, 0)
     B.close()
 
 
