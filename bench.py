@@ -25,6 +25,23 @@ import time
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
+# Calibrated HBM traffic of one k_factor launch on this workload, from
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch, FETCH scaled by
+# 2.0 and WRITE by 1.0 against a 1 GiB device copy), keyed by the sha256
+# prefix of the kernel source it was measured on.
+MEASURED_TRAFFIC = {
+    ("302bbe62b467df0a", "fp64"): {"fetch_bytes": 4938508.19 * 2.0 * 1024,
+                                   "write_bytes": 10345458.88 * 1.0 * 1024},
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "paper_2211_14969_amd", "csrc", "hps_kernels.hip")
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
 
 def algorithmic_flops(p: int):
     """Useful FLOP per leaf, per kernel: LU of A_ii together with the forward
@@ -167,6 +184,11 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "per_launch_flop": fl["factor"] * L, "launch_ms": t_factor},
     }
+    tr = MEASURED_TRAFFIC.get((kernel_source_hash(), args.prec))
+    if tr is not None:
+        line["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
+        line["roofline"]["traffic_detail"] = dict(tr, unit="bytes per launch",
+                                                  source="rocprofv3 --pmc, calibrated")
 
     if not args.no_compare:
         other = hps.HPS_FP32_REFINE if prec == hps.HPS_FP64 else hps.HPS_FP64
