@@ -24,6 +24,8 @@
 // among the rows not yet retired, ties to the lowest row index.
 #include <climits>
 #include <cmath>
+#include <type_traits>
+#include <utility>
 
 #include "hps_internal.h"
 
@@ -65,6 +67,7 @@ struct Tile;
 template <>
 struct Tile<double> {
   __device__ static __forceinline__ int inner(int r, int c) { return ((r & 15) << 4) + (c & 15); }
+  __device__ static __forceinline__ int crow(int q, int lane) { return 4 * q + (lane >> 4); }
   __device__ static __forceinline__ void rc(int w, int &r, int &c) {
     r = w >> 4;
     c = w & 15;
@@ -75,6 +78,7 @@ struct Tile<float> {
   __device__ static __forceinline__ int inner(int r, int c) {
     return ((r & 3) << 6) + (((r >> 2) & 3) << 4) + (c & 15);
   }
+  __device__ static __forceinline__ int crow(int q, int lane) { return 4 * (lane >> 4) + q; }
   __device__ static __forceinline__ void rc(int w, int &r, int &c) {
     const int q = w >> 6, ln = w & 63;
     r = 4 * (ln >> 4) + q;
@@ -207,6 +211,114 @@ __global__ void __launch_bounds__(256) k_build(Geom g, int mode, T *M, const dou
   }
 }
 
+// Pivot search key of one candidate row: the magnitude's leading bits (exact
+// for FP32; the top 32 bits of the FP64 pattern, i.e. 20 mantissa bits, so
+// candidates within a relative 2^-20 of the largest count as ties) above the
+// row index, complemented so that ties go to the lowest row.  Magnitudes of
+// non-negative IEEE values order like their bit patterns; NaN sorts above
+// infinity and is picked first, so it propagates.  0 marks "not a candidate".
+__device__ __forceinline__ unsigned long long pivot_key(double v, int r) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
+  return ((unsigned long long)hi << 32) | (unsigned)(0x7fffffff - r);
+}
+__device__ __forceinline__ unsigned long long pivot_key(float v, int r) {
+  const unsigned m = __float_as_uint(fabsf(v));
+  return ((unsigned long long)m << 32) | (unsigned)(0x7fffffff - r);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_max_step(unsigned long long v) {
+  const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+  const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo;
+  return o > v ? o : v;
+}
+
+// Maximum of a 64-bit key over the wavefront with DPP moves (quad
+// permutations, row shifts, then the row broadcasts of lanes 15 and 31);
+// lane 63 ends with the maximum, which is read back to every lane.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  v = dpp_max_step<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_max_step<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// One column C of the single-wavefront panel elimination.  The panel rows of
+// a lane live in v[t][*] (row lane + 64t); C is a template argument so that
+// every register index is static.
+template <typename T, int C>
+__device__ __forceinline__ void panel_column(T (&v)[4][16], unsigned &act, int lane, int R,
+                                             int k, int *pv, int *rst, int *zeroPiv) {
+  unsigned long long key = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if ((act >> t) & 1u) {
+      const unsigned long long kt = pivot_key(v[t][C], lane + 64 * t);
+      key = kt > key ? kt : key;
+    }
+  }
+  key = wave_max_u64(key);
+  int pr = 0x7fffffff - (int)(unsigned)(key & 0xffffffffu);
+  pr = (pr >= 0 && pr < R) ? pr : R - 1;
+  const int pt = pr >> 6, pl = pr & 63;
+  if (lane == pl) act &= ~(1u << pt);
+  // the pivot row (register pt of lane pl) is read into scalar registers;
+  // every lane selects its register pt, lane pl's value is then broadcast
+  // (no memory round trip, so no cross-lane ordering question)
+  using B = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type;
+  const B m1 = (B)0 - (B)(pt & 1), m2 = (B)0 - (B)((pt >> 1) & 1);
+  T pw[16];
+#pragma unroll
+  for (int cc = C; cc < 16; ++cc) {
+    B b0, b1, b2, b3;
+    __builtin_memcpy(&b0, &v[0][cc], sizeof(T));
+    __builtin_memcpy(&b1, &v[1][cc], sizeof(T));
+    __builtin_memcpy(&b2, &v[2][cc], sizeof(T));
+    __builtin_memcpy(&b3, &v[3][cc], sizeof(T));
+    const B b01 = (b0 & ~m1) | (b1 & m1), b23 = (b2 & ~m1) | (b3 & m1);
+    const B bs = (b01 & ~m2) | (b23 & m2);
+    B br;
+    if constexpr (sizeof(T) == 8) {
+      const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)bs, pl);
+      const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(bs >> 32), pl);
+      br = ((B)hi << 32) | lo;
+    } else {
+      br = (B)__builtin_amdgcn_readlane((int)bs, pl);
+    }
+    __builtin_memcpy(&pw[cc], &br, sizeof(T));
+  }
+  const T pval = pw[C];
+  if (lane == 0) {
+    pv[C] = pr;
+    rst[pr] = k;
+    if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + C + 1;
+  }
+  const T inv = (pval != T(0)) ? T(1) / pval : T(0);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if ((act >> t) & 1u) {
+      const T l = v[t][C] * inv;
+      v[t][C] = l;
+#pragma unroll
+      for (int cc = C + 1; cc < 16; ++cc) v[t][cc] -= l * pw[cc];
+    }
+  }
+}
+
+template <typename T, int... Cs>
+__device__ __forceinline__ void panel_columns(T (&v)[4][16], unsigned &act, int lane, int R, int k,
+                                              int *pv, int *rst, int *zeroPiv,
+                                              std::integer_sequence<int, Cs...>) {
+  (panel_column<T, Cs>(v, act, lane, R, k, pv, rst, zeroPiv), ...);
+}
+
 // ---------------------------------------------------------------------------
 // factor: blocked LU with implicit partial pivoting, MFMA trailing updates
 // ---------------------------------------------------------------------------
@@ -219,7 +331,7 @@ __device__ __forceinline__ T abs_key(T v) {
 }
 
 template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rstep,
+__global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv, int *rstep,
                                                int *info, int CH, Sel sel) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -230,7 +342,8 @@ __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rste
   const int UST = CH + 16;
   T *P = (T *)smem;                       // [R][kPST]   panel
   T *U = P + (size_t)R * kPST;            // [16][UST]   U12 chunk
-  T *redv = U + 16 * UST;                 // [NW]
+  T *Linv = U + 16 * UST;                 // [16][kPST]  inverse of L11
+  T *redv = Linv + 16 * kPST;             // [NW]
   int *rst = (int *)(redv + NW);          // [R]         retire step
   int *tileAct = rst + R;                 // [RT]
   int *pv = tileAct + RT;                 // [16]
@@ -250,95 +363,173 @@ __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rste
     __syncthreads();
 
     // --- panel: 16 columns of unblocked elimination in LDS ---
-    for (int c = 0; c < 16; ++c) {
-      T best = T(-1);
-      int bi = INT_MAX;
-      for (int r = tid; r < R; r += NT) {
-        if (rst[r] != kInfoActive) continue;
-        const T v = abs_key(P[r * kPST + c]);
-        if (v > best) { best = v; bi = r; }
-      }
+    if constexpr (NT == 256) {
+      // One wavefront: lane l owns rows l, l+64, l+128, l+192 and keeps
+      // their active bits in a register, so no workgroup barrier is needed
+      // between columns (LDS accesses of one wave are ordered).
+      if (wv == 0) {
+        // one wavefront, the panel in registers: lane l owns rows
+        // l + 64t (t < 4); the pivot search is a DPP maximum of pivot_key.
+        T v[4][16];
+        unsigned act = 0;
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
-      __syncthreads();
-      best = redv[0];
-      bi = redi[0];
+        for (int t = 0; t < 4; ++t) {
+          const int r = lane + 64 * t;
+          const bool in = r < R;
+          if (in && rst[r] == kInfoActive) act |= 1u << t;
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const T ob = redv[w];
-        const int oi = redi[w];
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      // R - (16k + c) >= 1 rows are active, so bi is a valid row; the clamp
-      // only guards the memory access.
-      const int pr = bi < R ? bi : R - 1;
-      const T pval = P[pr * kPST + c];
-      if (tid == 0) {
-        pv[c] = pr;
-        rst[pr] = k;
-        if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + c + 1;
-      }
-      const T inv = (pval != T(0)) ? T(1) / pval : T(0);
-      for (int r = tid; r < R; r += NT) {
-        if (r == pr || rst[r] != kInfoActive) continue;
-        const T l = P[r * kPST + c] * inv;
-        P[r * kPST + c] = l;
-        for (int cc = c + 1; cc < 16; ++cc) P[r * kPST + cc] -= l * P[pr * kPST + cc];
+          for (int c = 0; c < 16; ++c) v[t][c] = in ? P[r * kPST + c] : T(0);
+        }
+        panel_columns<T>(v, act, lane, R, k, pv, rst, zeroPiv,
+                         std::make_integer_sequence<int, 16>());
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int r = lane + 64 * t;
+          if (r < R) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) P[r * kPST + c] = v[t][c];
+          }
+        }
       }
       __syncthreads();
+    } else {
+      for (int c = 0; c < 16; ++c) {
+        T best = T(-1);
+        int bi = INT_MAX;
+        for (int r = tid; r < R; r += NT) {
+          if (rst[r] != kInfoActive) continue;
+          const T v = abs_key(P[r * kPST + c]);
+          if (v > best) { best = v; bi = r; }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ob = __shfl_xor(best, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
+        __syncthreads();
+        best = redv[0];
+        bi = redi[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          const T ob = redv[w];
+          const int oi = redi[w];
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        // R - (16k + c) >= 1 rows are active, so bi is a valid row; the clamp
+        // only guards the memory access.
+        const int pr = bi < R ? bi : R - 1;
+        const T pval = P[pr * kPST + c];
+        if (tid == 0) {
+          pv[c] = pr;
+          rst[pr] = k;
+          if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + c + 1;
+        }
+        const T inv = (pval != T(0)) ? T(1) / pval : T(0);
+        for (int r = tid; r < R; r += NT) {
+          if (r == pr || rst[r] != kInfoActive) continue;
+          const T l = P[r * kPST + c] * inv;
+          P[r * kPST + c] = l;
+          for (int cc = c + 1; cc < 16; ++cc) P[r * kPST + cc] -= l * P[pr * kPST + cc];
+        }
+        __syncthreads();
+      }
     }
 
+    // L11^{-1} (unit lower triangular, rows in pivot order): column j of the
+    // inverse by forward substitution in lane j of wave 0
+    if (wv == 0 && lane < 16) {
+      const int j = lane;
+      T x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T acc = (i == j) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < i; ++q) acc -= P[pv[i] * kPST + q] * x[q];
+        x[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Linv[i * kPST + j] = x[i];
+    }
     for (int t = tid; t < RT; t += NT) {
       int a = 0;
       for (int q = 0; q < 16; ++q) a |= (rst[t * 16 + q] == kInfoActive);
       tileAct[t] = a;
     }
+    __syncthreads();
 
     // --- U12 = L11^{-1} A12 and the trailing update, in column chunks ---
     const int cend = CT * 16;
     for (int c0 = (k + 1) * 16; c0 < cend; c0 += CH) {
       const int cw = min(CH, cend - c0);
-      for (int cc = tid; cc < cw; cc += NT) {
-        T u[16];
-#pragma unroll
-        for (int s = 0; s < 16; ++s) u[s] = Ml[tix<T>(pv[s], c0 + cc, CT)];
-#pragma unroll
-        for (int s = 1; s < 16; ++s) {
-          T acc = u[s];
-#pragma unroll
-          for (int q = 0; q < s; ++q) acc -= P[pv[s] * kPST + q] * u[q];
-          u[s] = acc;
-        }
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          U[s * UST + cc] = u[s];
-          Ml[tix<T>(pv[s], c0 + cc, CT)] = u[s];
-        }
+      // gather the raw pivot rows of the chunk (16 contiguous elements of a
+      // row per tile)
+      for (int e = tid; e < 16 * cw; e += NT) {
+        const int sr = e / cw, cc = e - sr * cw;
+        U[sr * UST + cc] = Ml[tix<T>(pv[sr], c0 + cc, CT)];
       }
       __syncthreads();
-      const int ntj = cw >> 4;
-      for (int t = wv; t < RT * ntj; t += NW) {
-        const int ti = t / ntj, tj = t - ti * ntj;
-        if (!tileAct[ti]) continue;
-        T *Ct = Ml + ((size_t)(ti * CT + (c0 >> 4) + tj) << 8);
+      // U12 = L11^{-1} A12 on MFMA, one tile per wave at a time, in place in
+      // U; the pivot rows of W receive their U12 entries
+      for (int jl = wv; jl < (cw >> 4); jl += NW) {
         typename Mfma<T>::acc acc;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = Ct[q * 64 + lane];
-        const int ar = ti * 16 + (lane & 15);
-        const bool act = rst[ar] == kInfoActive;
+        for (int q = 0; q < 4; ++q) acc[q] = T(0);
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
-          const T a = act ? -P[ar * kPST + 4 * kc + (lane >> 4)] : T(0);
-          const T b = U[(4 * kc + (lane >> 4)) * UST + tj * 16 + (lane & 15)];
+          const T a = Linv[(lane & 15) * kPST + 4 * kc + (lane >> 4)];
+          const T b = U[(4 * kc + (lane >> 4)) * UST + jl * 16 + (lane & 15)];
           acc = Mfma<T>::op(a, b, acc);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ct[q * 64 + lane] = acc[q];
+        for (int q = 0; q < 4; ++q) {
+          const int sr = Tile<T>::crow(q, lane);
+          const int cc = jl * 16 + (lane & 15);
+          U[sr * UST + cc] = acc[q];
+          Ml[tix<T>(pv[sr], c0 + cc, CT)] = acc[q];
+        }
+      }
+      __syncthreads();
+      // strips of up to four column tiles of one row tile per wave: all
+      // loads of a strip are in flight together and the A operand is shared
+      const int ntj = cw >> 4;
+      const int nstrip = (ntj + 3) >> 2;
+      for (int t = wv; t < RT * nstrip; t += NW) {
+        const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+        if (!tileAct[ti]) continue;
+        const int nj = min(4, ntj - j0);
+        T *Ct = Ml + ((size_t)(ti * CT + (c0 >> 4) + j0) << 8);
+        typename Mfma<T>::acc acc[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj < nj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[jj][q] = Ct[jj * 256 + q * 64 + lane];
+          }
+        }
+        const int ar = ti * 16 + (lane & 15);
+        const bool act = rst[ar] == kInfoActive;
+        T a[4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) a[kc] = act ? -P[ar * kPST + 4 * kc + (lane >> 4)] : T(0);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj < nj) {
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+              const T b = U[(4 * kc + (lane >> 4)) * UST + (j0 + jj) * 16 + (lane & 15)];
+              acc[jj] = Mfma<T>::op(a[kc], b, acc[jj]);
+            }
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj < nj) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = acc[jj][q];
+          }
+        }
       }
       __syncthreads();
     }
@@ -352,6 +543,55 @@ __global__ void __launch_bounds__(NT) k_factor(Geom g, T *M, int *piv, int *rste
   }
   for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
   if (tid == 0) info[leaf] = *zeroPiv;
+}
+
+// Right-hand-side update of the triangular solves:  C -= A * Y for every
+// row tile with a qualifying row, where A = W[rows, panel k] (rows retired
+// after step k for the forward replay, before it for the back substitution;
+// other rows contribute zero) and Y the 16 solved rows in LDS.  Each wave
+// takes a row tile and up to four right-hand-side tiles at once.
+template <typename T, int NW>
+__device__ __forceinline__ void strip_update(T *Ml, const T *Y, int YST, const int *rst,
+                                             const int *tileAny, int RT, int CT, int R, int ntj,
+                                             int k, bool after, int wv, int lane) {
+  const int nstrip = (ntj + 3) >> 2;
+  for (int t = wv; t < RT * nstrip; t += NW) {
+    const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+    if (!tileAny[ti]) continue;
+    const int nj = min(4, ntj - j0);
+    T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
+    typename Mfma<T>::acc acc[4];
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      if (jj < nj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[jj][q] = Ct[jj * 256 + q * 64 + lane];
+      }
+    }
+    const int ar = ti * 16 + (lane & 15);
+    const bool use = after ? rst[ar] > k : rst[ar] < k;
+    T a[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc)
+      a[kc] = use ? -Ml[tix<T>(ar, k * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      if (jj < nj) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const T b = Y[(4 * kc + (lane >> 4)) * YST + (j0 + jj) * 16 + (lane & 15)];
+          acc[jj] = Mfma<T>::op(a[kc], b, acc[jj]);
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      if (jj < nj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = acc[jj][q];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -403,25 +643,8 @@ __global__ void __launch_bounds__(NT) k_fwdsolve(Geom g, T *M, const int *piv,
       }
     }
     __syncthreads();
-    const int ntj = NRC >> 4;
-    for (int t = wv; t < RT * ntj; t += NW) {
-      const int ti = t / ntj, tj = t - ti * ntj;
-      if (!tileAny[ti]) continue;
-      T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + tj) << 8);
-      typename Mfma<T>::acc acc;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = Ct[q * 64 + lane];
-      const int ar = ti * 16 + (lane & 15);
-      const bool use = rst[ar] > k;
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) {
-        const T a = use ? -Ml[tix<T>(ar, k * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
-        const T b = Y[(4 * kc + (lane >> 4)) * YST + tj * 16 + (lane & 15)];
-        acc = Mfma<T>::op(a, b, acc);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Ct[q * 64 + lane] = acc[q];
-    }
+    strip_update<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k, /*after=*/true, wv,
+                        lane);
     __syncthreads();
   }
 }
@@ -500,25 +723,8 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
     }
     __syncthreads();
     if (k > 0) {
-      const int ntj = NRC >> 4;
-      for (int t = wv; t < RT * ntj; t += NW) {
-        const int ti = t / ntj, tj = t - ti * ntj;
-        if (!tileAny[ti]) continue;
-        T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + tj) << 8);
-        typename Mfma<T>::acc acc;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = Ct[q * 64 + lane];
-        const int ar = ti * 16 + (lane & 15);
-        const bool use = rst[ar] < k;
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-          const T a = use ? -Ml[tix<T>(ar, k * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
-          const T b = Y[(4 * kc + (lane >> 4)) * YST + tj * 16 + (lane & 15)];
-          acc = Mfma<T>::op(a, b, acc);
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Ct[q * 64 + lane] = acc[q];
-      }
+      strip_update<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k, /*after=*/false, wv,
+                          lane);
       __syncthreads();
     }
   }
@@ -832,24 +1038,30 @@ __global__ void k_copy_int(const int *src, int *dst, int n) {
   if (i < n) dst[i] = src[i];
 }
 
-constexpr int kFactorNT = 512;
 constexpr int kSolveNT = 256;
+
+// Workgroup size of the factorisation: 4 waves when one wave factors the
+// panel (R <= 256) so that several leaves share a CU; 8 waves otherwise.
+inline int factor_nt(const Geom &g) { return g.R <= 256 ? 256 : 512; }
 
 template <typename T>
 size_t factor_lds(const Geom &g, int CH) {
-  constexpr int NW = kFactorNT / 64;
-  size_t b = sizeof(T) * ((size_t)g.R * kPST + 16 * (size_t)(CH + 16) + NW);
+  const int NW = factor_nt(g) / 64;
+  size_t b = sizeof(T) * ((size_t)g.R * kPST + 16 * (size_t)(CH + 16) + 16 * kPST + NW);
   b += sizeof(int) * ((size_t)g.R + g.RT + 16 + NW + 1);
   return b;
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
+// Column chunk of the U12 buffer: 128 columns for the small orders (keeps
+// LDS low enough for several workgroups per CU), else as wide as fits.
 template <typename T>
 int pick_ch(const Geom &g) {
   const int full = g.CT * 16;
-  for (int ch = 512; ch >= 16; ch -= 16) {
-    const int c = ch < full ? ch : ((full + 15) / 16) * 16;
+  const int top = g.R <= 256 ? 128 : 512;
+  for (int ch = top; ch >= 16; ch -= 16) {
+    const int c = ch < full ? ch : full;
     if (factor_lds<T>(g, c) <= kLdsLimit) return c;
   }
   return 0;
@@ -898,18 +1110,32 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
     const int ch = pick_ch<float>(g);
     if (!ch) return hipErrorInvalidValue;
     const size_t lds = factor_lds<float>(g, ch);
-    hipError_t e = set_lds(k_factor<float, kFactorNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_factor<float, kFactorNT>), dim3(nleaf), dim3(kFactorNT), lds, s, g,
-                       (float *)M, piv, rstep, info, ch, sel);
+    if (factor_nt(g) == 256) {
+      hipError_t e = set_lds(k_factor<float, 256>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_factor<float, 256>), dim3(nleaf), dim3(256), lds, s, g, (float *)M,
+                         piv, rstep, info, ch, sel);
+    } else {
+      hipError_t e = set_lds(k_factor<float, 512>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_factor<float, 512>), dim3(nleaf), dim3(512), lds, s, g, (float *)M,
+                         piv, rstep, info, ch, sel);
+    }
   } else {
     const int ch = pick_ch<double>(g);
     if (!ch) return hipErrorInvalidValue;
     const size_t lds = factor_lds<double>(g, ch);
-    hipError_t e = set_lds(k_factor<double, kFactorNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_factor<double, kFactorNT>), dim3(nleaf), dim3(kFactorNT), lds, s, g,
-                       (double *)M, piv, rstep, info, ch, sel);
+    if (factor_nt(g) == 256) {
+      hipError_t e = set_lds(k_factor<double, 256>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_factor<double, 256>), dim3(nleaf), dim3(256), lds, s, g,
+                         (double *)M, piv, rstep, info, ch, sel);
+    } else {
+      hipError_t e = set_lds(k_factor<double, 512>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_factor<double, 512>), dim3(nleaf), dim3(512), lds, s, g,
+                         (double *)M, piv, rstep, info, ch, sel);
+    }
   }
   return hipGetLastError();
 }
