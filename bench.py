@@ -30,8 +30,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # 2.0 and WRITE by 1.0 against a 1 GiB device copy), keyed by the sha256
 # prefix of the kernel source it was measured on.
 MEASURED_TRAFFIC = {
-    ("302bbe62b467df0a", "fp64"): {"fetch_bytes": 4938508.19 * 2.0 * 1024,
-                                   "write_bytes": 10345458.88 * 1.0 * 1024},
+    ("f8d45915e423d4c7", "fp64"): {"fetch_bytes": 3002244.875 * 2.0 * 1024,
+                                   "write_bytes": 8168565.406 * 1.0 * 1024},
 }
 
 
@@ -95,6 +95,11 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32+refinement comparison run")
+    ap.add_argument("--workload", default="bump",
+                    choices=("bump", "tiny", "bumps", "annulus", "uneven"),
+                    help="bump: 64x64 leaves p=16 (default, the headline configuration); "
+                         "tiny: 4x4 p=8; bumps: 32x32 p=32; annulus: 128x16 p=20; "
+                         "uneven: the eight-problem batch p=8..32 in one batch")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM traffic counters against a known byte count)")
@@ -123,10 +128,14 @@ def main() -> int:
         print(json.dumps({"copy_mib": args.copy_mib, "copies": 3}))
         return 0
     hps.load()
-    prob = inputs.single_bump()
-    p, L = prob.p, prob.nleaf
-    print(f"# workload {prob.name}: {L} leaves, p={p}", file=sys.stderr, flush=True)
-    B = LeafBatch([prob])
+    probs = {"bump": lambda: [inputs.single_bump()], "tiny": lambda: [inputs.tiny()],
+             "bumps": lambda: [inputs.multi_bump()], "annulus": lambda: [inputs.annulus()],
+             "uneven": lambda: inputs.uneven_batch()}[args.workload]()
+    prob = probs[0]
+    p, L = prob.p, sum(q.nleaf for q in probs)
+    print(f"# workload {args.workload}: {L} leaves, p={[q.p for q in probs]}", file=sys.stderr,
+          flush=True)
+    B = LeafBatch(probs)
     S, w, info = B.alloc_outputs()
     prec = hps.HPS_FP64 if args.prec == "fp64" else hps.HPS_FP32_REFINE
 
@@ -153,10 +162,13 @@ def main() -> int:
     phases = hps.hps_ctx_phase_times(B.ctx)
     hps.hps_ctx_set_timing(B.ctx, False)
     bad = int((info != 0).sum().item())
+    redo = hps.hps_batch_stats(B.batch)[1]
 
-    fl = algorithmic_flops(p)
+    fl = {k: sum(algorithmic_flops(q.p)[k] * q.nleaf for q in probs) / L
+          for k in ("factor", "backsolve", "schur", "total")}
     f_ms, f_n = phases["factor"]
-    t_factor = f_ms / max(f_n, 1)
+    t_factor = f_ms / args.steps          # ms of factorisation launches per step
+    launch_ms = f_ms / max(f_n, 1)        # average duration of one launch
     dtype = "f64" if args.prec == "fp64" else "f32+f64"
     peak = PEAK_TFLOPS["fp64" if args.prec == "fp64" else "fp32"]
     achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
@@ -174,15 +186,19 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": prob.name, "leaves": L, "p": p, "kappa": prob.kappa,
+        "config": {"workload": prob.name if len(probs) == 1 else "uneven_8_problems",
+                   "leaves": L, "p": p if len(probs) == 1 else [q.p for q in probs],
+                   "kappa": prob.kappa if len(probs) == 1 else [q.kappa for q in probs],
                    "b": prob.meta.get("b"), "precision": args.prec, "parallelism": "single-gpu"},
         "useful_tflops": fl["total"] * L / (ms * 1e-3) / 1e12,
         "useful_frac_fp64_peak": fl["total"] * L / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
         "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items() if v[1]},
         "leaves_with_nonzero_info": bad,
+        "leaves_redone_fp64": redo,
         "roofline": {"bound": "mfma", "kernel": "k_factor", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "per_launch_flop": fl["factor"] * L, "launch_ms": t_factor},
+                     "per_launch_flop": fl["factor"] * L * args.steps / max(f_n, 1),
+                     "launch_ms": launch_ms, "launches_per_step": f_n / args.steps},
     }
     tr = MEASURED_TRAFFIC.get((kernel_source_hash(), args.prec))
     if tr is not None:
@@ -205,10 +221,13 @@ def main() -> int:
         e1.record()
         torch.cuda.synchronize()
         ms2 = e0.elapsed_time(e1) / n2
-        nb = 4 * (p - 2)
-        Sa, Sb = S.view(L, nb, nb), S2.view(L, nb, nb)
-        rel = ((Sa - Sb).flatten(1).norm(dim=1) / Sa.flatten(1).norm(dim=1)).max().item()
+        rel = 0.0
+        for Sa, Sb in zip(B.split(S, "S"), B.split(S2, "S")):
+            rel = max(rel, ((Sa - Sb).flatten(1).norm(dim=1)
+                            / Sa.flatten(1).norm(dim=1)).max().item())
+        redo2 = hps.hps_batch_stats(B.batch)[1]
         line["compare"] = {"precision": "fp32+refine" if other == hps.HPS_FP32_REFINE else "fp64",
+                           "leaves_redone_fp64": redo2,
                            "leaves_per_s": L / (ms2 * 1e-3), "ms_per_step": ms2,
                            "max_refine": args.max_refine,
                            "max_leaf_relerr_S_vs_other": rel}
@@ -216,6 +235,8 @@ def main() -> int:
     if not args.no_cpu:
         print("# timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        if len(probs) > 1:
+            line["cpu_baseline"]["sample"] += f" (first problem, p={prob.p})"
     B.close()
     print(json.dumps(line), flush=True)
     return 0

@@ -129,11 +129,13 @@ hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib,
  *   prec       : HPS_FP64 or HPS_FP32_REFINE
  *   tol        : refinement target (HPS_FP32_REFINE; ignored for HPS_FP64):
  *                a leaf stops refining when the estimated relative forward
- *                error of X, (||r_k|| / ||r_{k-1}||) ||dX_k|| / ||X_k|| from
- *                the FP64 residuals r = A_ib - A_ii X, is at most tol, or
- *                when its normwise backward error
- *                ||r|| / (||A_ii|| ||X|| + ||[A_ib f_i]||) is at FP64
- *                rounding level.  <= 0 selects 1e-10.
+ *                error of X, rho ||dX_k|| / ||X_k||, is at most tol, with
+ *                dX_k the last correction and rho the contraction per step,
+ *                estimated as the larger of ||r_k|| / ||r_{k-1}|| and
+ *                ||dX_1|| / ||X_1|| (r = A_ib - A_ii X evaluated in FP64).
+ *                <= 0 selects 1e-10; >= 1 applies exactly max_refine
+ *                corrections and accepts the result without a test (no
+ *                FP64 redo).
  *   max_refine : FP32 correction steps at most, 0..16.  The residual is
  *                evaluated before each correction and once more after the
  *                last.  Leaves that never pass (A_ii too ill-conditioned for
@@ -165,6 +167,18 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol,
 hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
                             double *ui, int flags);
 
+/* Tuning of group g's factorisation (for an autotuner; the defaults are
+ * chosen automatically):
+ *   factor_variant : 0 automatic, 1 one 16-column panel per trailing pass,
+ *                    2 panels in pairs (one trailing pass per 32 columns;
+ *                    used only when (p-2)^2 <= 256)
+ *   chunk_cols     : 0 automatic, else the column width (multiple of 16, at
+ *                    most 1024) of the U12 / trailing passes; ignored when
+ *                    its LDS footprint does not fit.
+ * Results do not depend on the tuning beyond rounding.  Takes effect on the
+ * next hps_leaf_condense / hps_leaf_recover. */
+hps_status hps_batch_set_tuning(hps_batch *b, int g, int factor_variant, int chunk_cols);
+
 /* Copy the stored FP64 solution operator out of the batch:
  *   Xt : device [total leaves][nb][ni]  (X transposed: Xt[l][b][i] = X_l[i][b])
  *   h  : device [total leaves][ni]
@@ -180,14 +194,15 @@ hps_status hps_batch_stats(const hps_batch *b, int *refine_steps, int *fp64_redo
 /* Per-phase timing with HIP events on the context stream (tracing aid).
  * While enabled, every kernel launch of hps_leaf_condense / hps_leaf_recover
  * is bracketed by events and the elapsed time is accumulated per phase:
- *   0 operator build   1 LU factorisation (with forward elimination of the
- *   right-hand sides)   2 back substitution   3 refinement (residual,
- *   forward replay, back substitution, convergence test)   4 Schur
- *   complement   5 recovery.
+ *   0 (unused)   1 operator build and LU factorisation (with forward
+ *   elimination of the right-hand sides)   2 back substitution
+ *   3 refinement correction solves and stop tests   4 Schur complement
+ *   5 recovery   6 refinement FP64 residuals   7 FP64 redo of leaves the
+ *   refinement could not serve.
  * hps_ctx_phase_times synchronises the stream, writes the accumulated
  * milliseconds and launch counts of the HPS_NPHASE phases (host arrays,
  * either may be NULL) and resets them. */
-#define HPS_NPHASE 6
+#define HPS_NPHASE 8
 hps_status hps_ctx_set_timing(hps_ctx *ctx, int enable);
 hps_status hps_ctx_phase_times(hps_ctx *ctx, double *ms, int *launches);
 

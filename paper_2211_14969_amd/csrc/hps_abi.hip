@@ -36,6 +36,8 @@ struct Group {
   size_t s_off;         // offset of the group's S block (doubles)
   size_t b_off;         // offset of the group's w / ub block (doubles)
   double *dtab;         // device: t [p], D [p*p], D2 [p*p]
+  int tune_variant;     // see hps_batch_set_tuning
+  int tune_ch;
 };
 
 hps_status from_hip(hipError_t e) {
@@ -135,6 +137,15 @@ hps::Geom make_geom(const hps_leaf_desc &d, const double *dtab, int nrhs) {
   g.k2b = d.k2b;
   g.D = dtab + d.p;
   g.D2 = dtab + d.p + (size_t)d.p * d.p;
+  g.tune_variant = 0;
+  g.tune_ch = 0;
+  return g;
+}
+
+hps::Geom make_geom(const Group &G, int nrhs) {
+  hps::Geom g = make_geom(G.d, G.dtab, nrhs);
+  g.tune_variant = G.tune_variant;
+  g.tune_ch = G.tune_ch;
   return g;
 }
 
@@ -163,7 +174,7 @@ hps_status ensure_workspace(hps_batch *b, bool refactor, int extra, bool fp32,
   size_t need = 0, need_pr = 0;
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     const Group &G = b->groups[gi];
-    const hps::Geom g = make_geom(G.d, G.dtab, rhs_cols(G, refactor, extra));
+    const hps::Geom g = make_geom(G, rhs_cols(G, refactor, extra));
     const size_t per = work_bytes_per_leaf(g, fp32);
     size_t chunk = std::max<size_t>(1, b->ws_limit / per);
     chunk = std::min<size_t>(chunk, (size_t)G.d.nleaf);
@@ -322,6 +333,8 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
     G.d = groups[i];
     G.leaf0 = leaf0;
     G.dtab = nullptr;
+    G.tune_variant = 0;
+    G.tune_ch = 0;
     const int p = G.d.p;
     std::vector<double> tab((size_t)p + 2 * (size_t)p * p);
     hps::cheb_tables(p, tab.data(), tab.data() + p, tab.data() + p + (size_t)p * p);
@@ -403,7 +416,7 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
   const int extra = f ? 1 : 0;
   std::vector<int> chunk(b->groups.size());
   for (const Group &G : b->groups)
-    if (hps::factor_lds_bytes(make_geom(G.d, G.dtab, G.geom.nb + extra), fp32) == 0)
+    if (hps::factor_lds_bytes(make_geom(G, G.geom.nb + extra), fp32) == 0)
       return HPS_ERR_INVALID;
   hps_status st = ensure_workspace(b, false, extra, fp32, chunk.data());
   if (st != HPS_OK) return st;
@@ -412,7 +425,7 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
   HPS_TRY(hps::launch_fill_int(b->count, 2, 0, s));
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     const Group &G = b->groups[gi];
-    const hps::Geom g0 = make_geom(G.d, G.dtab, G.geom.nb + extra);
+    const hps::Geom g0 = make_geom(G, G.geom.nb + extra);
     for (int l0 = 0; l0 < G.d.nleaf; l0 += chunk[gi]) {
       const int n = std::min(chunk[gi], G.d.nleaf - l0);
       const hps::Geom g = shift(g0, l0);
@@ -421,8 +434,10 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
       double *Xt = b->Xt + G.xt_off + (size_t)l0 * g.nb * g.ni;
       double *hh = f ? b->h + G.h_off + (size_t)l0 * g.ni : nullptr;
       int *inf = b->info + gl;
-      HPS_TRY(timed(b->ctx, 0, [&] { return hps::launch_build(g, n, hps::RHS_CONDENSE, fp32, b->ws, fc, nullptr, s); }));
-      HPS_TRY(timed(b->ctx, 1, [&] { return hps::launch_factor(g, n, fp32, b->ws, b->piv, b->rstep, inf, s); }));
+      HPS_TRY(timed(b->ctx, 1, [&] {
+        return hps::launch_factor(g, n, fp32, b->ws, b->piv, b->rstep, inf, hps::RHS_CONDENSE, fc,
+                                  nullptr, s);
+      }));
       hps::BackOut o;
       o.Xt = Xt;
       o.h = hh;
@@ -442,7 +457,8 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
         o.skip = conv;
         o.norms = nrm;
         for (int it = 0; it <= nref; ++it) {
-          HPS_TRY(timed(b->ctx, 3, [&] {
+          if (it == nref && it > 0 && tl >= 1.0) break;  // no final test wanted
+          HPS_TRY(timed(b->ctx, 6, [&] {
             return hps::launch_residual(g, n, (float *)b->ws, Xt, hh, fc, conv, nrm, s);
           }));
           HPS_TRY(timed(b->ctx, 3, [&] {
@@ -476,13 +492,11 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
           sel.count = b->count;
           sel.slot0 = s0;
           const int nb_ = std::min(cap, n - s0);
-          HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_build(g, nb_, hps::RHS_CONDENSE, false, b->ws, fc, nullptr, s, sel);
+          HPS_TRY(timed(b->ctx, 7, [&] {
+            return hps::launch_factor(g, nb_, false, b->ws, b->piv, b->rstep, inf,
+                                      hps::RHS_CONDENSE, fc, nullptr, s, sel);
           }));
-          HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_factor(g, nb_, false, b->ws, b->piv, b->rstep, inf, s, sel);
-          }));
-          HPS_TRY(timed(b->ctx, 3, [&] {
+          HPS_TRY(timed(b->ctx, 7, [&] {
             return hps::launch_backsolve(g, nb_, false, b->ws, b->piv, b->rstep, o64, s, sel);
           }));
         }
@@ -511,7 +525,7 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
     if (st != HPS_OK) return st;
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
       const Group &G = b->groups[gi];
-      const hps::Geom g0 = make_geom(G.d, G.dtab, 1);
+      const hps::Geom g0 = make_geom(G, 1);
       const int ch = chunk[gi];
       for (int l0 = 0; l0 < G.d.nleaf; l0 += ch) {
         const int n = std::min(ch, G.d.nleaf - l0);
@@ -520,10 +534,8 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
         const double *uc = ub + G.b_off + (size_t)l0 * g.nb;
         int *inf = b->info + G.leaf0 + l0;
         HPS_TRY(timed(b->ctx, 5, [&] {
-          return hps::launch_build(g, n, hps::RHS_REFACTOR, false, b->ws, fc, uc, s);
-        }));
-        HPS_TRY(timed(b->ctx, 5, [&] {
-          return hps::launch_factor(g, n, false, b->ws, b->piv, b->rstep, inf, s);
+          return hps::launch_factor(g, n, false, b->ws, b->piv, b->rstep, inf, hps::RHS_REFACTOR,
+                                    fc, uc, s);
         }));
         hps::BackOut o;
         o.Xt = nullptr;
@@ -549,6 +561,15 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
     }));
   }
   if (flags & HPS_SYNC) HPS_TRY(hipStreamSynchronize(s));
+  return HPS_OK;
+}
+
+hps_status hps_batch_set_tuning(hps_batch *b, int g, int factor_variant, int chunk_cols) {
+  if (!b || g < 0 || g >= (int)b->groups.size()) return HPS_ERR_INVALID;
+  if (factor_variant < 0 || factor_variant > 2) return HPS_ERR_INVALID;
+  if (chunk_cols < 0 || chunk_cols > 1024 || (chunk_cols & 15)) return HPS_ERR_INVALID;
+  b->groups[g].tune_variant = factor_variant;
+  b->groups[g].tune_ch = chunk_cols;
   return HPS_OK;
 }
 

@@ -21,6 +21,8 @@ struct Geom {
   const double *a11, *a22, *c1, *c2, *k2b;  // [nleaf][p*p] or nullptr
   const double *D;                          // [p][p]  d/dt on [-1, 1]
   const double *D2;                         // [p][p]  D*D
+  int tune_variant;   // factorisation: 0 automatic, 1 one panel per pass, 2 panel pairs
+  int tune_ch;        // column chunk of the U12 / trailing passes (0 automatic)
 };
 
 // Right-hand-side layouts of the work matrix.
@@ -56,11 +58,11 @@ struct BackOut {
 constexpr int kInfoActive = 0x7fffffff;
 
 // Launchers (hps_kernels.hip).  All enqueue on `s` and return hipError_t.
-hipError_t launch_build(const Geom &g, int nleaf, int mode, bool fp32, void *M,
-                        const double *f, const double *ub, hipStream_t s,
-                        const Sel &sel = Sel());
+// Factorisation of the work matrices; step 0 forms them from the operator
+// (mode RHS_CONDENSE with optional f, or RHS_REFACTOR with f and ub).
 hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
-                         int *rstep, int *info, hipStream_t s, const Sel &sel = Sel());
+                         int *rstep, int *info, int mode, const double *f, const double *ub,
+                         hipStream_t s, const Sel &sel = Sel());
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
                             const int *piv, const int *rstep, const BackOut &o,
                             hipStream_t s, const Sel &sel = Sel());

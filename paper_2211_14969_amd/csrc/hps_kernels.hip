@@ -22,8 +22,10 @@
 //
 // The pivoting follows LAPACK getrf: the largest magnitude in the column
 // among the rows not yet retired, ties to the lowest row index.
+#include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
 
@@ -44,6 +46,7 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+#ifdef HPS_F32_NATIVE_MFMA
 template <>
 struct Mfma<float> {
   using acc = f4;
@@ -51,6 +54,20 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
+#else
+// FP32 work matrices take their tile products on the FP64 MFMA: the FP32
+// operands are exact in FP64, so every product is exact and accumulation is
+// FP64 before rounding back to FP32 storage.  (The FP32 16x16x4 instruction
+// rounds its operands more coarsely, which leaves the factorisation too
+// inexact for FP64 refinement to converge on the higher orders.)
+template <>
+struct Mfma<float> {
+  using acc = d4;
+  __device__ static __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, (double)b, c, 0, 0, 0);
+  }
+};
+#endif
 
 // Element (r, c) of a tile-major work matrix with CT column tiles.  Inside a
 // 16 x 16 tile the 256 elements are ordered as the accumulator registers of
@@ -73,6 +90,7 @@ struct Tile<double> {
     c = w & 15;
   }
 };
+#ifdef HPS_F32_NATIVE_MFMA
 template <>
 struct Tile<float> {
   __device__ static __forceinline__ int inner(int r, int c) {
@@ -85,6 +103,10 @@ struct Tile<float> {
     c = ln & 15;
   }
 };
+#else
+template <>
+struct Tile<float> : Tile<double> {};   // FP64 MFMA accumulator order
+#endif
 
 template <typename T>
 __device__ __forceinline__ size_t tix(int r, int c, int CT) {
@@ -158,57 +180,41 @@ __device__ __forceinline__ void stage_tables(const Geom &g, double *sD, double *
   }
 }
 
-// ---------------------------------------------------------------------------
-// build: form W = [A_ii | rhs] of every leaf (operator step of Sec. 2)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_build(Geom g, int mode, T *M, const double *f,
-                                               const double *ub, Sel sel) {
-  __shared__ double sD[32 * 32], sD2[32 * 32];
-  int leaf;
-  if (!resolve_leaf(sel, leaf)) return;
-  stage_tables(g, sD, sD2);
-  __syncthreads();
-  const LeafScale sc = leaf_scale(g, leaf);
-  const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R, CT = g.CT;
+// Element (r, c) of the work matrix W = [A_ii | rhs] of one leaf (r, c
+// counted in the padded layout), formed from the operator: used by the
+// factorisation's first step, which builds W instead of reading it.
+struct BuildSrc {
+  int mode;           // RHS_CONDENSE or RHS_REFACTOR
+  const double *f;    // [nleaf][ni] or nullptr (leaf-indexed like the geometry)
+  const double *ub;   // [nleaf][nb] (RHS_REFACTOR)
+};
+
+__device__ __forceinline__ double build_elem(const Geom &g, LeafScale sc, int leaf,
+                                             const BuildSrc &bs, int r, int c) {
+  const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R;
+  if (r >= ni) return (c == r) ? 1.0 : 0.0;
   const size_t nbase = (size_t)leaf * p * p;
-  T *Ml = M + leaf_stride(g) * blockIdx.x;
-  const size_t total = leaf_stride(g);
-  for (size_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int tile = (int)(e >> 8);
-    int ri, ci;
-    Tile<T>::rc((int)(e & 255), ri, ci);
-    const int r = (tile / CT) * 16 + ri;
-    const int c = (tile % CT) * 16 + ci;
-    double v = 0.0;
-    if (r >= ni) {
-      v = (c == r) ? 1.0 : 0.0;
-    } else {
-      const int i = r % m + 1, j = r / m + 1;
-      if (c < ni) {
-        v = opval(g, sD, sD2, sc, nbase, i, j, c % m + 1, c / m + 1);
-      } else if (c >= R) {
-        const int jr = c - R;
-        if (mode == RHS_CONDENSE) {
-          if (jr < nb) {
-            int k, l;
-            bnode(jr, m, p, k, l);
-            v = opval(g, sD, sD2, sc, nbase, i, j, k, l);
-          } else if (jr == nb && f) {
-            v = f[(size_t)leaf * ni + r];
-          }
-        } else if (jr == 0) {  // RHS_REFACTOR: f_i - A_ib u_b
-          const double *u = ub + (size_t)leaf * nb;
-          v = f ? f[(size_t)leaf * ni + r] : 0.0;
-          v -= opval(g, sD, sD2, sc, nbase, i, j, 0, j) * u[j - 1];
-          v -= opval(g, sD, sD2, sc, nbase, i, j, p - 1, j) * u[m + j - 1];
-          v -= opval(g, sD, sD2, sc, nbase, i, j, i, 0) * u[2 * m + i - 1];
-          v -= opval(g, sD, sD2, sc, nbase, i, j, i, p - 1) * u[3 * m + i - 1];
-        }
-      }
+  const int i = r % m + 1, j = r / m + 1;
+  if (c < ni) return opval(g, g.D, g.D2, sc, nbase, i, j, c % m + 1, c / m + 1);
+  if (c < R) return 0.0;
+  const int jr = c - R;
+  if (bs.mode == RHS_CONDENSE) {
+    if (jr < nb) {
+      int k, l;
+      bnode(jr, m, p, k, l);
+      return opval(g, g.D, g.D2, sc, nbase, i, j, k, l);
     }
-    Ml[e] = (T)v;
+    if (jr == nb && bs.f) return bs.f[(size_t)leaf * ni + r];
+    return 0.0;
   }
+  if (jr != 0) return 0.0;
+  const double *u = bs.ub + (size_t)leaf * nb;  // RHS_REFACTOR: f_i - A_ib u_b
+  double v = bs.f ? bs.f[(size_t)leaf * ni + r] : 0.0;
+  v -= opval(g, g.D, g.D2, sc, nbase, i, j, 0, j) * u[j - 1];
+  v -= opval(g, g.D, g.D2, sc, nbase, i, j, p - 1, j) * u[m + j - 1];
+  v -= opval(g, g.D, g.D2, sc, nbase, i, j, i, 0) * u[2 * m + i - 1];
+  v -= opval(g, g.D, g.D2, sc, nbase, i, j, i, p - 1) * u[3 * m + i - 1];
+  return v;
 }
 
 // Pivot search key of one candidate row: the magnitude's leading bits (exact
@@ -332,7 +338,7 @@ __device__ __forceinline__ T abs_key(T v) {
 
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv, int *rstep,
-                                               int *info, int CH, Sel sel) {
+                                                        int *info, int CH, Sel sel, BuildSrc bs) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -350,9 +356,21 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
   int *redi = pv + 16;                    // [NW]
   int *zeroPiv = redi + NW;               // [1]
   T *Ml = M + leaf_stride(g) * wi;
+  const LeafScale sc = leaf_scale(g, leaf);
 
   for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
   if (tid == 0) *zeroPiv = 0;
+  // form W from the operator (coalesced, tile-major); the leaf's matrix is
+  // read back by this workgroup right away, mostly from cache
+  {
+    const size_t total = leaf_stride(g);
+    for (size_t e = tid; e < total; e += NT) {
+      const int tile = (int)(e >> 8);
+      int ri, ci;
+      Tile<T>::rc((int)(e & 255), ri, ci);
+      Ml[e] = (T)build_elem(g, sc, leaf, bs, (tile / CT) * 16 + ri, (tile % CT) * 16 + ci);
+    }
+  }
   __syncthreads();
 
   for (int k = 0; k < RT; ++k) {
@@ -555,43 +573,347 @@ __device__ __forceinline__ void strip_update(T *Ml, const T *Y, int YST, const i
                                              const int *tileAny, int RT, int CT, int R, int ntj,
                                              int k, bool after, int wv, int lane) {
   const int nstrip = (ntj + 3) >> 2;
-  for (int t = wv; t < RT * nstrip; t += NW) {
+  const int nall = RT * nstrip;
+  auto next_strip = [&](int t) {
+    while (t < nall && !tileAny[t / nstrip]) t += NW;
+    return t;
+  };
+  typename Mfma<T>::acc cur[4], nxt[4];
+  T acur[4], anxt[4];
+  // loads of a strip: its C tiles and its A operand (W[rows, panel k])
+  auto load_strip = [&](int t, typename Mfma<T>::acc (&dst)[4], T (&a)[4]) {
     const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
-    if (!tileAny[ti]) continue;
     const int nj = min(4, ntj - j0);
-    T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
-    typename Mfma<T>::acc acc[4];
+    const T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       if (jj < nj) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[jj][q] = Ct[jj * 256 + q * 64 + lane];
+        for (int q = 0; q < 4; ++q) dst[jj][q] = Ct[jj * 256 + q * 64 + lane];
       }
     }
     const int ar = ti * 16 + (lane & 15);
     const bool use = after ? rst[ar] > k : rst[ar] < k;
-    T a[4];
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc)
       a[kc] = use ? -Ml[tix<T>(ar, k * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
+  };
+  int t = next_strip(wv);
+  if (t < nall) load_strip(t, cur, acur);
+  while (t < nall) {
+    const int tn = next_strip(t + NW);
+    if (tn < nall) load_strip(tn, nxt, anxt);
+    const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+    const int nj = min(4, ntj - j0);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       if (jj < nj) {
 #pragma unroll
         for (int kc = 0; kc < 4; ++kc) {
           const T b = Y[(4 * kc + (lane >> 4)) * YST + (j0 + jj) * 16 + (lane & 15)];
-          acc[jj] = Mfma<T>::op(a[kc], b, acc[jj]);
+          cur[jj] = Mfma<T>::op(acur[kc], b, cur[jj]);
         }
       }
     }
+    T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       if (jj < nj) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = acc[jj][q];
+        for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = cur[jj][q];
       }
     }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) cur[jj] = nxt[jj];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) acur[kc] = anxt[kc];
+    t = tn;
   }
+}
+
+// ---------------------------------------------------------------------------
+// factor2: the same factorisation for R <= 256 with panels taken in pairs.
+// Panel A's update is applied at once only to panel B's column tile; panel
+// B is factored, and the rest of the trailing matrix then receives both
+// updates in one pass (C -= L21_A U12_A + L21_B U12_B, 8 MFMAs per tile), so
+// the trailing matrix streams through memory half as often.  The pivot rows
+// of B take panel A's update on the way: U12_B = L11_B^{-1} (A12_B -
+// L21_A[B] U12_A).  The stored form (multipliers in the panel columns, U rows
+// in the pivot rows, retire steps) is exactly that of k_factor.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void panel_one_wave(T *P, int R, int k, int lane, int *pv, int *rst,
+                                               int *zeroPiv) {
+  T v[4][16];
+  unsigned act = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = lane + 64 * t;
+    const bool in = r < R;
+    if (in && rst[r] == kInfoActive) act |= 1u << t;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[t][c] = in ? P[r * kPST + c] : T(0);
+  }
+  panel_columns<T>(v, act, lane, R, k, pv, rst, zeroPiv, std::make_integer_sequence<int, 16>());
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = lane + 64 * t;
+    if (r < R) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) P[r * kPST + c] = v[t][c];
+    }
+  }
+}
+
+// L11^{-1} of a factored panel (unit lower triangular, rows in pivot order);
+// lane j < 16 forms column j by forward substitution.
+template <typename T>
+__device__ __forceinline__ void linv16(const T *P, const int *pv, T *Linv, int lane) {
+  if (lane < 16) {
+    const int j = lane;
+    T x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      T acc = (i == j) ? T(1) : T(0);
+#pragma unroll
+      for (int q = 0; q < i; ++q) acc -= P[pv[i] * kPST + q] * x[q];
+      x[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Linv[i * kPST + j] = x[i];
+  }
+}
+
+// D (16x16 tile, accumulator layout) = L (16x16, LDS row-major stride kPST)
+// times the tile of B at column offset bc in a row-major LDS block.
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::acc tri_apply(const T *L, const T *B, int BST, int bc,
+                                                           int lane) {
+  typename Mfma<T>::acc acc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = T(0);
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const T a = L[(lane & 15) * kPST + 4 * kc + (lane >> 4)];
+    const T b = B[(4 * kc + (lane >> 4)) * BST + bc + (lane & 15)];
+    acc = Mfma<T>::op(a, b, acc);
+  }
+  return acc;
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256, 2) k_factor2(Geom g, T *M, int *piv, int *rstep,
+                                                    int *info, int CH, Sel sel, BuildSrc bs) {
+  constexpr int NT = 256, NW = 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  const int R = g.R, RT = g.RT, CT = g.CT;
+  const int UST = CH + 16;
+  T *PA = (T *)smem;                      // [R][kPST]  panel A
+  T *PB = PA + (size_t)R * kPST;          // [R][kPST]  panel B
+  T *U = PB + (size_t)R * kPST;           // [32][UST]  raw / U12 rows of A (0..15), B (16..31)
+  T *LA = U + 32 * UST;                   // [16][kPST] L11_A^{-1}
+  T *LB = LA + 16 * kPST;                 // [16][kPST] L11_B^{-1}
+  int *rst = (int *)(LB + 16 * kPST);     // [R]
+  int *tileAct = rst + R;                 // [RT]
+  int *pvA = tileAct + RT;                // [16]
+  int *pvB = pvA + 16;                    // [16]
+  int *zeroPiv = pvB + 16;                // [1]
+  T *Ml = M + leaf_stride(g) * wi;
+  const LeafScale sc = leaf_scale(g, leaf);
+
+  for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
+  if (tid == 0) *zeroPiv = 0;
+  {
+    const size_t total = leaf_stride(g);
+    for (size_t e = tid; e < total; e += NT) {
+      const int tile = (int)(e >> 8);
+      int ri, ci;
+      Tile<T>::rc((int)(e & 255), ri, ci);
+      Ml[e] = (T)build_elem(g, sc, leaf, bs, (tile / CT) * 16 + ri, (tile % CT) * 16 + ci);
+    }
+  }
+  __syncthreads();
+
+  auto load_panel = [&](T *Pb, int k) {
+    for (int e = tid; e < R * 16; e += NT) {
+      const int r = e >> 4, c = e & 15;
+      Pb[r * kPST + c] = Ml[tix<T>(r, k * 16 + c, CT)];
+    }
+  };
+  auto factor_panel = [&](T *Pb, int k, int *pv, T *Li) {
+    if (wv == 0) {
+      panel_one_wave<T>(Pb, R, k, lane, pv, rst, zeroPiv);
+      // pv and rst were written by lane 0 alone: order those writes before
+      // the other lanes read them
+      wave_lds_fence<T>();
+      linv16<T>(Pb, pv, Li, lane);
+      for (int t = lane; t < RT; t += 64) {
+        int a = 0;
+        for (int q = 0; q < 16; ++q) a |= (rst[t * 16 + q] == kInfoActive);
+        tileAct[t] = a;
+      }
+    }
+  };
+  // C -= sum over the panels in use of L21 U12, strips of up to 4 tiles of
+  // one row tile per wave; the next strip's tiles are loaded before the
+  // current strip's MFMAs so that two strips per wave are in flight.
+  auto trailing = [&](int c0, int cw, bool two) {
+    const int ntj = cw >> 4;
+    const int nstrip = (ntj + 3) >> 2;
+    const int nall = RT * nstrip;
+    auto next_strip = [&](int t) {
+      while (t < nall && !tileAct[t / nstrip]) t += NW;
+      return t;
+    };
+    typename Mfma<T>::acc cur[4], nxt[4];
+    auto load_strip = [&](int t, typename Mfma<T>::acc (&dst)[4]) {
+      const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+      const int nj = min(4, ntj - j0);
+      const T *Ct = Ml + ((size_t)(ti * CT + (c0 >> 4) + j0) << 8);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dst[jj][q] = Ct[jj * 256 + q * 64 + lane];
+        }
+      }
+    };
+    int t = next_strip(wv);
+    if (t < nall) load_strip(t, cur);
+    while (t < nall) {
+      const int tn = next_strip(t + NW);
+      if (tn < nall) load_strip(tn, nxt);
+      const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+      const int nj = min(4, ntj - j0);
+      const int ar = ti * 16 + (lane & 15);
+      const bool act = rst[ar] == kInfoActive;
+      T a[8];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        a[kc] = act ? -PA[ar * kPST + 4 * kc + (lane >> 4)] : T(0);
+        a[4 + kc] = (act && two) ? -PB[ar * kPST + 4 * kc + (lane >> 4)] : T(0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const T b = U[(4 * kc + (lane >> 4)) * UST + (j0 + jj) * 16 + (lane & 15)];
+            cur[jj] = Mfma<T>::op(a[kc], b, cur[jj]);
+          }
+          if (two) {
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+              const T b = U[(16 + 4 * kc + (lane >> 4)) * UST + (j0 + jj) * 16 + (lane & 15)];
+              cur[jj] = Mfma<T>::op(a[4 + kc], b, cur[jj]);
+            }
+          }
+        }
+      }
+      T *Ct = Ml + ((size_t)(ti * CT + (c0 >> 4) + j0) << 8);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = cur[jj][q];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) cur[jj] = nxt[jj];
+      t = tn;
+    }
+  };
+  // Pivot rows of A (and B) over columns [c0, c0+cw): U12 rows, stored in W.
+  auto u12 = [&](int c0, int cw, bool two) {
+    const int nrow = two ? 32 : 16;
+    for (int e = tid; e < nrow * cw; e += NT) {
+      const int sr = e / cw, cc = e - sr * cw;
+      const int row = sr < 16 ? pvA[sr] : pvB[sr - 16];
+      U[sr * UST + cc] = Ml[tix<T>(row, c0 + cc, CT)];
+    }
+    __syncthreads();
+    for (int jl = wv; jl < (cw >> 4); jl += NW) {
+      const int cb = jl * 16 + (lane & 15);
+      typename Mfma<T>::acc ua = tri_apply<T>(LA, U, UST, jl * 16, lane);
+      wave_lds_fence<T>();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int sr = Tile<T>::crow(q, lane);
+        U[sr * UST + cb] = ua[q];
+        Ml[tix<T>(pvA[sr], c0 + cb, CT)] = ua[q];
+      }
+      if (two) {
+        wave_lds_fence<T>();
+        // raw rows of B minus panel A's update: U_B - L21_A[pvB] U12_A
+        typename Mfma<T>::acc ub;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ub[q] = U[(16 + Tile<T>::crow(q, lane)) * UST + cb];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const T a = -PA[pvB[lane & 15] * kPST + 4 * kc + (lane >> 4)];
+          const T b = U[(4 * kc + (lane >> 4)) * UST + cb];
+          ub = Mfma<T>::op(a, b, ub);
+        }
+        wave_lds_fence<T>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[(16 + Tile<T>::crow(q, lane)) * UST + cb] = ub[q];
+        wave_lds_fence<T>();
+        typename Mfma<T>::acc u2 = tri_apply<T>(LB, U + 16 * UST, UST, jl * 16, lane);
+        wave_lds_fence<T>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int sr = Tile<T>::crow(q, lane);
+          U[(16 + sr) * UST + cb] = u2[q];
+          Ml[tix<T>(pvB[sr], c0 + cb, CT)] = u2[q];
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  for (int k = 0; k < RT; k += 2) {
+    const bool two = k + 1 < RT;
+    load_panel(PA, k);
+    __syncthreads();
+    factor_panel(PA, k, pvA, LA);
+    __syncthreads();
+    if (two) {
+      // panel A's update of panel B's column tile only
+      u12(16 * (k + 1), 16, false);
+      trailing(16 * (k + 1), 16, false);
+      __syncthreads();
+      load_panel(PB, k + 1);
+      __syncthreads();
+      factor_panel(PB, k + 1, pvB, LB);
+      __syncthreads();
+    }
+    const int cend = CT * 16;
+    for (int c0 = 16 * (k + (two ? 2 : 1)); c0 < cend; c0 += CH) {
+      const int cw = min(CH, cend - c0);
+      u12(c0, cw, two);
+      trailing(c0, cw, two);
+      __syncthreads();
+    }
+    for (int e = tid; e < R * 16; e += NT) {
+      const int r = e >> 4, c = e & 15;
+      Ml[tix<T>(r, k * 16 + c, CT)] = PA[r * kPST + c];
+      if (two) Ml[tix<T>(r, (k + 1) * 16 + c, CT)] = PB[r * kPST + c];
+    }
+    if (tid < 16) piv[(size_t)wi * R + k * 16 + tid] = pvA[tid];
+    if (two && tid >= 16 && tid < 32) piv[(size_t)wi * R + (k + 1) * 16 + tid - 16] = pvB[tid - 16];
+    __syncthreads();
+  }
+  for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
+  if (tid == 0) info[leaf] = *zeroPiv;
 }
 
 // ---------------------------------------------------------------------------
@@ -749,11 +1071,16 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
 // correction solve, and the squared Frobenius norms of r, X, A_ii and
 // [A_ib f_i] are stored per leaf for the backward-error stop test.
 // ---------------------------------------------------------------------------
+constexpr int kResRows = 4;    // rows per thread: R <= 4 * 256
+constexpr int kResCols = 8;    // columns of [X h] staged per pass
+
 __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const double *Xt,
                                                   const double *h, const double *f,
-                                                  const int *skip, double *norms) {
-  __shared__ double sD[32 * 32], sD2[32 * 32];
-  __shared__ double xcol[30 * 30];
+                                                  const int *skip, double *norms, int RC) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *sD = (double *)smem;               // [p*p]
+  double *sD2 = sD + g.p * g.p;              // [p*p]
+  double *xs = sD2 + g.p * g.p;              // [RC][ni] staged columns of [X h]
   __shared__ double red[4][4];
   const int leaf = blockIdx.x;
   if (skip && skip[leaf]) return;
@@ -763,55 +1090,114 @@ __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const doub
   const size_t nbase = (size_t)leaf * p * p;
   float *Ml = M32 + leaf_stride(g) * leaf;
   const int ncol = (h && f) ? nb + 1 : nb;
+  // per-row operator data in registers: the x1-line and x2-line weights
+  // come from D and D^2 scaled by the row's coefficients
+  double ax2[kResRows], ax1[kResRows], ay2[kResRows], ay1[kResRows], kb[kResRows];
+  double bw[kResRows][4], fr[kResRows];
+  int ri[kResRows], rj[kResRows];
   double nr = 0.0, nx = 0.0, na = 0.0, nbb = 0.0;
-  for (int jr = 0; jr < ncol; ++jr) {
-    __syncthreads();
-    const double *src = (jr < nb) ? Xt + ((size_t)leaf * nb + jr) * ni : h + (size_t)leaf * ni;
-    for (int e = threadIdx.x; e < ni; e += blockDim.x) xcol[e] = src[e];
-    __syncthreads();
-    for (int r = threadIdx.x; r < R; r += blockDim.x) {
-      double res = 0.0;
-      if (r < ni) {
-        const int i = r % m + 1, j = r / m + 1;
-        const size_t n = nbase + i + (size_t)p * j;
-        const double a11 = g.a11 ? g.a11[n] : 1.0, c1 = g.c1 ? g.c1[n] : 0.0;
-        const double a22 = g.a22 ? g.a22[n] : 1.0, c2 = g.c2 ? g.c2[n] : 0.0;
-        const double k2b = g.k2b ? g.k2b[n] : 0.0;
-        const double ax2 = a11 * sc.sx * sc.sx, ax1 = c1 * sc.sx;
-        const double ay2 = a22 * sc.sy * sc.sy, ay1 = c2 * sc.sy;
-        double ax = -k2b * xcol[r];
-        for (int k = 1; k <= m; ++k)
-          ax -= (ax2 * sD2[i * p + k] + ax1 * sD[i * p + k]) * xcol[(k - 1) + m * (j - 1)];
-        for (int l = 1; l <= m; ++l)
-          ax -= (ay2 * sD2[j * p + l] + ay1 * sD[j * p + l]) * xcol[(i - 1) + m * (l - 1)];
-        double bval;
-        if (jr < nb) {
-          int k, l;
-          bnode(jr, m, p, k, l);
-          bval = opval(g, sD, sD2, sc, nbase, i, j, k, l);
-        } else {
-          bval = f[(size_t)leaf * ni + r];
-        }
-        res = bval - ax;
-        nr += res * res;
-        nx += xcol[r] * xcol[r];
-        nbb += bval * bval;
-        if (jr == 0) {
-          // squared norm of row r of A_ii: off-diagonal x1- and x2-line
-          // entries, and the diagonal where both lines and k2b meet
-          double diag = -k2b;
-          for (int k = 1; k <= m; ++k) {
-            const double v = -(ax2 * sD2[i * p + k] + ax1 * sD[i * p + k]);
-            if (k == i) diag += v; else na += v * v;
-          }
-          for (int l = 1; l <= m; ++l) {
-            const double v = -(ay2 * sD2[j * p + l] + ay1 * sD[j * p + l]);
-            if (l == j) diag += v; else na += v * v;
-          }
-          na += diag * diag;
-        }
+#pragma unroll
+  for (int t = 0; t < kResRows; ++t) {
+    const int r = threadIdx.x + 256 * t;
+    ri[t] = 0;
+    rj[t] = 0;
+    ax2[t] = ax1[t] = ay2[t] = ay1[t] = kb[t] = fr[t] = 0.0;
+    bw[t][0] = bw[t][1] = bw[t][2] = bw[t][3] = 0.0;
+    if (r < ni) {
+      const int i = r % m + 1, j = r / m + 1;
+      ri[t] = i;
+      rj[t] = j;
+      const size_t n = nbase + i + (size_t)p * j;
+      const double a11 = g.a11 ? g.a11[n] : 1.0, c1 = g.c1 ? g.c1[n] : 0.0;
+      const double a22 = g.a22 ? g.a22[n] : 1.0, c2 = g.c2 ? g.c2[n] : 0.0;
+      kb[t] = g.k2b ? g.k2b[n] : 0.0;
+      ax2[t] = a11 * sc.sx * sc.sx;
+      ax1[t] = c1 * sc.sx;
+      ay2[t] = a22 * sc.sy * sc.sy;
+      ay1[t] = c2 * sc.sy;
+      fr[t] = (h && f) ? f[(size_t)leaf * ni + r] : 0.0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kResRows; ++t) {
+    const int r = threadIdx.x + 256 * t;
+    if (r < ni) {
+      const int i = ri[t], j = rj[t];
+      // A_ib row: the four edge nodes on the row's two grid lines (W, E, S, N)
+      bw[t][0] = -(ax2[t] * sD2[i * p + 0] + ax1[t] * sD[i * p + 0]);
+      bw[t][1] = -(ax2[t] * sD2[i * p + p - 1] + ax1[t] * sD[i * p + p - 1]);
+      bw[t][2] = -(ay2[t] * sD2[j * p + 0] + ay1[t] * sD[j * p + 0]);
+      bw[t][3] = -(ay2[t] * sD2[j * p + p - 1] + ay1[t] * sD[j * p + p - 1]);
+      // squared norm of row r of A_ii (the diagonal joins both lines and k2b)
+      double diag = -kb[t];
+      for (int k = 1; k <= m; ++k) {
+        const double v = -(ax2[t] * sD2[i * p + k] + ax1[t] * sD[i * p + k]);
+        if (k == i) diag += v; else na += v * v;
       }
-      Ml[tix<float>(r, R + jr, CT)] = (float)res;
+      for (int l = 1; l <= m; ++l) {
+        const double v = -(ay2[t] * sD2[j * p + l] + ay1[t] * sD[j * p + l]);
+        if (l == j) diag += v; else na += v * v;
+      }
+      na += diag * diag;
+      nbb += bw[t][0] * bw[t][0] + bw[t][1] * bw[t][1] + bw[t][2] * bw[t][2] +
+             bw[t][3] * bw[t][3] + fr[t] * fr[t];
+    }
+  }
+  for (int c0 = 0; c0 < ncol; c0 += RC) {
+    const int cw = min(RC, ncol - c0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cw * ni; e += blockDim.x) {
+      const int c = e / ni, i = e - c * ni, col = c0 + c;
+      xs[c * ni + i] = (col < nb) ? Xt[((size_t)leaf * nb + col) * ni + i]
+                                  : h[(size_t)leaf * ni + i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kResRows; ++t) {
+      const int r = threadIdx.x + 256 * t;
+      if (r >= R) continue;
+      if (r >= ni) {
+        for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = 0.0f;
+        continue;
+      }
+      const int i = ri[t], j = rj[t];
+      double acc[kResCols];
+#pragma unroll
+      for (int c = 0; c < kResCols; ++c) acc[c] = c < cw ? -kb[t] * xs[c * ni + r] : 0.0;
+      for (int k = 1; k <= m; ++k) {
+        const double wgt = ax2[t] * sD2[i * p + k] + ax1[t] * sD[i * p + k];
+        const int xi = (k - 1) + m * (j - 1);
+#pragma unroll
+        for (int c = 0; c < kResCols; ++c)
+          if (c < cw) acc[c] -= wgt * xs[c * ni + xi];
+      }
+      for (int l = 1; l <= m; ++l) {
+        const double wgt = ay2[t] * sD2[j * p + l] + ay1[t] * sD[j * p + l];
+        const int xi = (i - 1) + m * (l - 1);
+#pragma unroll
+        for (int c = 0; c < kResCols; ++c)
+          if (c < cw) acc[c] -= wgt * xs[c * ni + xi];
+      }
+#pragma unroll
+      for (int c = 0; c < kResCols; ++c) {
+        if (c >= cw) continue;
+        const int col = c0 + c;
+        double bval;
+        if (col == nb) {
+          bval = fr[t];
+        } else {
+          bval = 0.0;
+          if (col == j - 1) bval = bw[t][0];
+          else if (col == m + j - 1) bval = bw[t][1];
+          else if (col == 2 * m + i - 1) bval = bw[t][2];
+          else if (col == 3 * m + i - 1) bval = bw[t][3];
+        }
+        const double res = bval - acc[c];
+        nr += res * res;
+        nx += xs[c * ni + r] * xs[c * ni + r];
+        Ml[tix<float>(r, R + col, CT)] = (float)res;
+      }
     }
   }
   // block reduction of the four sums
@@ -837,25 +1223,30 @@ __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const doub
   }
 }
 
-// Stop test of the refinement, per leaf, after the residual r_k of X_k:
-//  * the normwise backward error ||r||/(||A_ii|| ||X|| + ||[A_ib f]||) is at
-//    the FP64 rounding level, or
-//  * the estimated forward error (||r_k|| / ||r_{k-1}||) ||dX_k||, i.e. the
-//    observed contraction of the residual times the last correction, is at
-//    most tol ||X_k||.
-// On the final check a leaf that passed neither is flagged -1.
-// norms[8l + ...]: 0 ||r||^2, 1 ||X||^2, 2 ||A_ii||^2, 3 ||[A_ib f]||^2,
-// 4 previous ||r||^2, 5 ||dX||^2 of the last correction.
+// Stop test of the refinement, per leaf, after the residual r_k of X_k: the
+// estimated forward error rho ||dX_k|| is at most tol ||X_k||, where dX_k is
+// the last correction and rho, the contraction factor of the iteration, is
+// the larger of two estimates: the observed contraction of the residual
+// ||r_k|| / ||r_{k-1}||, and the relative size of the first correction
+// ||dX_1|| / ||X_1||, i.e. the forward error of the low-precision solve,
+// which sets the contraction of LU-based refinement.  Either one alone can
+// underestimate the error several-fold on a nearly singular A_ii.  A leaf
+// whose iteration stalls above tol (its FP64 error floor, about
+// cond(A_ii) 2^-53, lies above tol) never passes.  An exactly zero residual
+// passes; tol >= 1 passes on the final check without a test.  On the final
+// check a leaf that did not pass is flagged -1.
+// norms[8l + ...]: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2, 5 ||dX||^2 of
+// the last correction, 6 the relative size of the first correction.
 __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
                             int it, int last) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaf || conv[l]) return;
   double *n = norms + 8 * (size_t)l;
-  const double eta = sqrt(n[0]) / (sqrt(n[2]) * sqrt(n[1]) + sqrt(n[3]));
-  bool ok = eta <= 4.0 * 0x1p-53;
-  if (!ok && it > 0 && n[4] > 0.0) {
-    const double est = sqrt(n[0] / n[4]) * sqrt(n[5]);
-    ok = est <= tol * sqrt(n[1]);
+  bool ok = n[0] == 0.0 || (tol >= 1.0 && last);
+  if (it == 1) n[6] = n[1] > 0.0 ? sqrt(n[5] / n[1]) : 1.0;
+  if (!ok && tol < 1.0 && it > 0 && n[4] > 0.0) {
+    const double rho = fmax(sqrt(n[0] / n[4]), n[6]);
+    ok = rho * sqrt(n[5]) <= tol * sqrt(n[1]);
   }
   n[4] = n[0];
   if (ok) {
@@ -1059,6 +1450,10 @@ constexpr size_t kLdsLimit = 160 * 1024;
 template <typename T>
 int pick_ch(const Geom &g) {
   const int full = g.CT * 16;
+  if (g.tune_ch > 0) {
+    const int c = g.tune_ch < full ? g.tune_ch : full;
+    if (factor_lds<T>(g, c) <= kLdsLimit) return c;
+  }
   const int top = g.R <= 256 ? 128 : 512;
   for (int ch = top; ch >= 16; ch -= 16) {
     const int c = ch < full ? ch : full;
@@ -1074,6 +1469,16 @@ size_t solve_lds(const Geom &g) {
   b += sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST);
   b += sizeof(int) * ((size_t)g.R + g.RT + 16);
   return b;
+}
+
+// Panels in pairs for R <= 256 (default); HPS_FACTOR_PAIRS=0 selects the
+// one-panel-per-pass kernel.
+bool factor_pairs_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("HPS_FACTOR_PAIRS");
+    return !(v && v[0] == '0');
+  }();
+  return on;
 }
 
 template <typename F>
@@ -1093,19 +1498,55 @@ size_t factor_lds_bytes(const Geom &g, bool fp32) {
   return ch ? factor_lds<double>(g, ch) : 0;
 }
 
-hipError_t launch_build(const Geom &g, int nleaf, int mode, bool fp32, void *M,
-                        const double *f, const double *ub, hipStream_t s, const Sel &sel) {
-  if (fp32)
-    hipLaunchKernelGGL(k_build<float>, dim3(nleaf), dim3(256), 0, s, g, mode, (float *)M, f, ub,
-                       sel);
-  else
-    hipLaunchKernelGGL(k_build<double>, dim3(nleaf), dim3(256), 0, s, g, mode, (double *)M, f, ub,
-                       sel);
+template <typename T>
+size_t factor2_lds(const Geom &g, int CH) {
+  size_t b = sizeof(T) * (2 * (size_t)g.R * kPST + 32 * (size_t)(CH + 16) + 32 * kPST);
+  b += sizeof(int) * ((size_t)g.R + g.RT + 33);
+  return b;
+}
+
+// Column chunk of factor2: the largest multiple of 16 (at most 128) that
+// leaves room for two workgroups per CU.
+template <typename T>
+int pick_ch2(const Geom &g) {
+  const int full = g.CT * 16;
+  if (g.tune_ch > 0) {
+    const int c = g.tune_ch < full ? g.tune_ch : full;
+    if (factor2_lds<T>(g, c) <= kLdsLimit) return c;
+  }
+  for (int ch = 128; ch >= 16; ch -= 16) {
+    const int c = ch < full ? ch : full;
+    if (factor2_lds<T>(g, c) <= kLdsLimit / 2) return c;
+  }
+  for (int ch = 128; ch >= 16; ch -= 16) {
+    const int c = ch < full ? ch : full;
+    if (factor2_lds<T>(g, c) <= kLdsLimit) return c;
+  }
+  return 0;
+}
+
+template <typename T>
+hipError_t launch_factor2(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
+                          const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  const int ch = pick_ch2<T>(g);
+  if (!ch) return hipErrorInvalidValue;
+  const size_t lds = factor2_lds<T>(g, ch);
+  hipError_t e = set_lds(k_factor2<T>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_factor2<T>, dim3(nleaf), dim3(256), lds, s, g, M, piv, rstep, info, ch, sel,
+                     bs);
   return hipGetLastError();
 }
 
 hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv, int *rstep,
-                         int *info, hipStream_t s, const Sel &sel) {
+                         int *info, int mode, const double *f, const double *ub, hipStream_t s,
+                         const Sel &sel) {
+  const BuildSrc bs{mode, f, ub};
+  const bool pairs = g.R <= 256 && g.tune_variant != 1 && factor_pairs_enabled();
+  if (pairs) {
+    if (fp32) return launch_factor2<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
+    return launch_factor2<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
+  }
   if (fp32) {
     const int ch = pick_ch<float>(g);
     if (!ch) return hipErrorInvalidValue;
@@ -1114,12 +1555,12 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
       hipError_t e = set_lds(k_factor<float, 256>, lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_factor<float, 256>), dim3(nleaf), dim3(256), lds, s, g, (float *)M,
-                         piv, rstep, info, ch, sel);
+                         piv, rstep, info, ch, sel, bs);
     } else {
       hipError_t e = set_lds(k_factor<float, 512>, lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_factor<float, 512>), dim3(nleaf), dim3(512), lds, s, g, (float *)M,
-                         piv, rstep, info, ch, sel);
+                         piv, rstep, info, ch, sel, bs);
     }
   } else {
     const int ch = pick_ch<double>(g);
@@ -1129,12 +1570,12 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
       hipError_t e = set_lds(k_factor<double, 256>, lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_factor<double, 256>), dim3(nleaf), dim3(256), lds, s, g,
-                         (double *)M, piv, rstep, info, ch, sel);
+                         (double *)M, piv, rstep, info, ch, sel, bs);
     } else {
       hipError_t e = set_lds(k_factor<double, 512>, lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL((k_factor<double, 512>), dim3(nleaf), dim3(512), lds, s, g,
-                         (double *)M, piv, rstep, info, ch, sel);
+                         (double *)M, piv, rstep, info, ch, sel, bs);
     }
   }
   return hipGetLastError();
@@ -1179,7 +1620,13 @@ hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M, const i
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip, double *norms,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(nleaf), dim3(256), 0, s, g, M32, Xt, h, f, skip, norms);
+  // columns staged per pass: as many as fit 48 KiB, at most 16
+  const int RC = kResCols;
+  const size_t lds = sizeof(double) * (2 * (size_t)g.p * g.p + (size_t)RC * g.ni);
+  hipError_t e = set_lds(k_residual, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residual, dim3(nleaf), dim3(256), lds, s, g, M32, Xt, h, f, skip, norms,
+                     RC);
   return hipGetLastError();
 }
 

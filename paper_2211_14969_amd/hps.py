@@ -35,11 +35,12 @@ EXPORTED = (
     "hps_status_string", "hps_ctx_create", "hps_ctx_destroy", "hps_leaf_build",
     "hps_batch_nleaf", "hps_batch_group_dims", "hps_leaf_nodes", "hps_leaf_operator",
     "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
-    "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times",
+    "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times", "hps_batch_set_tuning",
 )
 
-HPS_NPHASE = 6
-PHASES = ("build", "factor", "backsolve", "refine", "schur", "recover")
+HPS_NPHASE = 8
+PHASES = ("unused", "factor", "backsolve", "refine_solve", "schur", "recover", "refine_residual",
+          "fp64_redo")
 
 
 class hps_leaf_desc(ctypes.Structure):
@@ -101,6 +102,8 @@ def load(path: str = LIB_PATH):
     L.hps_batch_stats.argtypes = [vp, ctypes.POINTER(ip), ctypes.POINTER(ip)]
     L.hps_batch_destroy.restype = i
     L.hps_batch_destroy.argtypes = [vp]
+    L.hps_batch_set_tuning.restype = i
+    L.hps_batch_set_tuning.argtypes = [vp, i, i, i]
     L.hps_ctx_set_timing.restype = i
     L.hps_ctx_set_timing.argtypes = [vp, i]
     L.hps_ctx_phase_times.restype = i
@@ -237,3 +240,8 @@ def hps_ctx_phase_times(ctx: int):
     n = (ctypes.c_int * HPS_NPHASE)()
     _check(load().hps_ctx_phase_times(ctypes.c_void_p(ctx), ms, n), "hps_ctx_phase_times")
     return {PHASES[k]: (ms[k], n[k]) for k in range(HPS_NPHASE)}
+
+
+def hps_batch_set_tuning(batch: int, g: int, factor_variant: int = 0, chunk_cols: int = 0) -> None:
+    _check(load().hps_batch_set_tuning(ctypes.c_void_p(batch), int(g), int(factor_variant),
+                                       int(chunk_cols)), "hps_batch_set_tuning")

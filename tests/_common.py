@@ -39,3 +39,12 @@ def sample_leaves(nleaf, count, seed=0):
     idx = set(rng.choice(nleaf, size=k, replace=False).tolist())
     idx.update({0, nleaf - 1})
     return sorted(idx)
+
+
+def leaf_bar(Aii, tol):
+    """Per-leaf error bar: `tol`, or the FP64 floor 10 * cond_2(A_ii) * 2^-53
+    where that is larger.  A leaf close to a Dirichlet resonance of its box
+    has a nearly singular A_ii; the rounding of the operator entries alone
+    (a relative change of 2^-53 each, which two correct FP64 builds may
+    differ by) moves X by up to about cond(A_ii) * 2^-53 relative."""
+    return max(tol, 10.0 * float(np.linalg.cond(Aii)) * 2.0 ** -53)

@@ -12,7 +12,7 @@ import sys
 import numpy as np
 import pytest
 
-from _common import oracle_leaf, relerr, sample_leaves
+from _common import leaf_bar, oracle_leaf, relerr, sample_leaves
 from paper_2211_14969_amd import hps, inputs
 
 pytestmark = pytest.mark.gpu
@@ -50,12 +50,13 @@ def _check_sample(B, S, Xt, problems, tol, nsample, seed):
         prob = G.problem
         assert bool(torch_isfinite(Sg)), prob.name
         for t in sample_leaves(prob.nleaf, nsample, seed):
-            _, c = oracle_leaf(prob, t)
+            bl, c = oracle_leaf(prob, t)
+            bar = leaf_bar(bl.Aii, tol)
             eS = relerr(Sg[t].cpu().numpy(), c.S)
             eX = relerr(Xg[t].cpu().numpy().T, c.X)
             worst = max(worst, eS)
-            assert eS <= tol, (prob.name, t, eS)
-            assert eX <= max(tol, 1e-8), (prob.name, t, eX)
+            assert eS <= bar, (prob.name, t, eS, bar)
+            assert eX <= max(bar, 1e-8), (prob.name, t, eX, bar)
     return worst
 
 

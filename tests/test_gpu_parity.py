@@ -1,10 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
-Tolerances.  FP64 path: normwise relative error <= 1e-10 for the operator
-blocks' neighbours X, h, S, w (the condition numbers of A_ii on these
-workloads stay below ~1e6, so c * kappa * eps_64 is below 1e-9 and the
-measured error is far smaller).  FP32 + FP64 refinement: <= 1e-9 relative on
-S and on the recovered u, the target the method is built for.
+Tolerances, normwise relative error per leaf.  FP64 path: 1e-10 on X, h, S,
+w.  FP32 + FP64 refinement: 1e-9 on S, h, w and on the recovered u, the
+target the method is built for (1e-8 on X).  Either bar is raised to the
+FP64 floor 10 cond_2(A_ii) 2^-53 on a leaf where that is larger: a leaf near
+a Dirichlet resonance of its box (cond up to ~1e8 on the p = 32 grids here)
+cannot be pinned closer than that by any FP64 computation, since rounding
+the operator entries alone moves X that far.
 """
 import math
 import sys
@@ -12,7 +14,7 @@ import sys
 import numpy as np
 import pytest
 
-from _common import oracle_interior_f, oracle_leaf, relerr, sample_leaves
+from _common import leaf_bar, oracle_interior_f, oracle_leaf, relerr, sample_leaves
 from oracle import leaf as lf
 from oracle import interface as itf
 from paper_2211_14969_amd import hps, inputs
@@ -88,16 +90,18 @@ def _check_condense(torch, prob, prec, tol, with_x=True, leaves=None, max_refine
     S = S.view(prob.nleaf, nb, nb).cpu().numpy()
     Xt = Xt.view(prob.nleaf, nb, ni).cpu().numpy()
     assert np.all(info.cpu().numpy() == 0)
-    worst = {"S": 0.0, "X": 0.0}
+    worst = {"S": 0.0, "X": 0.0, "S/bar": 0.0}
     for t in (leaves if leaves is not None else range(prob.nleaf)):
-        _, c = oracle_leaf(prob, t)
+        bl, c = oracle_leaf(prob, t)
+        bar = leaf_bar(bl.Aii, tol)
         eS, eX = relerr(S[t], c.S), relerr(Xt[t].T, c.X)
         worst["S"] = max(worst["S"], eS)
         worst["X"] = max(worst["X"], eX)
+        worst["S/bar"] = max(worst["S/bar"], eS / bar)
+        assert eS <= bar, (t, eS, bar)
+        if with_x:
+            assert eX <= (bar if prec == hps.HPS_FP64 else max(bar, 1e-8)), (t, eX, bar)
     _say(f"  {prob.name} prec={prec} worst {worst}")
-    assert worst["S"] <= tol
-    if with_x:
-        assert worst["X"] <= (tol if prec == hps.HPS_FP64 else 1e-8)
     B.close()
     return worst
 
@@ -105,13 +109,13 @@ def _check_condense(torch, prob, prec, tol, with_x=True, leaves=None, max_refine
 @pytest.mark.parametrize("p", ORDERS)
 def test_condense_fp64_orders(torch, p):
     _say(f"condense fp64 p={p}")
-    _check_condense(torch, _small(p, 2, 3), hps.HPS_FP64, TOL64)
+    _check_condense(torch, _small(p, 3), hps.HPS_FP64, TOL64)
 
 
 @pytest.mark.parametrize("p", ORDERS)
 def test_condense_fp32_refine_orders(torch, p):
     _say(f"condense fp32+refine p={p}")
-    _check_condense(torch, _small(p, 3, 2), hps.HPS_FP32_REFINE, TOL_MIXED)
+    _check_condense(torch, _small(p, 3), hps.HPS_FP32_REFINE, TOL_MIXED)
 
 
 @pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
@@ -278,6 +282,33 @@ def test_refinement_stats_typical_leaves(torch):
     B = _batch([prob])
     S, w, info, st = B.condense(prec=hps.HPS_FP32_REFINE, max_refine=2, sync=True)
     assert hps.hps_batch_stats(B.batch) == (2, 0)
+    B.close()
+
+
+def test_fixed_step_count_without_stop_test(torch):
+    """tol >= 1 applies exactly max_refine corrections with no test and no
+    FP64 redo: the error in X falls with every step (the contraction of
+    LU-based refinement) until it reaches FP64 level."""
+    prob = _small(24, 2, 1)
+    _say("fixed step count")
+    B = _batch([prob])
+    ni, nb = (prob.p - 2) ** 2, 4 * (prob.p - 2)
+    ref = [oracle_leaf(prob, t)[1].X for t in range(prob.nleaf)]
+    errs = []
+    for k in range(4):
+        S, w, info = B.alloc_outputs()
+        st = hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 2.0, k, None, S, w, info,
+                                   hps.HPS_SYNC)
+        assert st == hps.HPS_OK
+        assert hps.hps_batch_stats(B.batch) == (k, 0)
+        Xt, _ = B.export()
+        Xt = Xt.view(prob.nleaf, nb, ni).cpu().numpy()
+        errs.append(max(relerr(Xt[t].T, ref[t]) for t in range(prob.nleaf)))
+    floor = max(leaf_bar(oracle_leaf(prob, t)[0].Aii, 0.0) for t in range(prob.nleaf))
+    _say(f"  X error after 0..3 corrections {errs}, FP64 floor {floor:.1e}")
+    assert 1e-9 < errs[0] < 1e-3
+    assert errs[1] < 1e-2 * errs[0]
+    assert errs[2] <= max(1e-2 * errs[1], floor) and errs[3] <= floor
     B.close()
 
 

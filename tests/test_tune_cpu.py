@@ -1,0 +1,32 @@
+"""Host logic of the autotuner: candidates, cache keys, cache round trip."""
+import os
+
+from paper_2211_14969_amd import hps, tune
+
+
+def test_buckets_and_keys():
+    assert tune.bucket(1) == 64 and tune.bucket(64) == 64 and tune.bucket(65) == 128
+    assert tune.bucket(4096) == 4096 and tune.bucket(4097) == 8192
+    assert tune.cache_key(16, hps.HPS_FP64, 4096) == "p16_fp64_L4096"
+    assert tune.cache_key(32, hps.HPS_FP32_REFINE, 1000) == "p32_fp32r_L1024"
+
+
+def test_candidates_respect_kernel_limits():
+    for p in (4, 8, 12, 16, 17, 18, 20, 32):
+        cands = tune.candidates(p)
+        assert cands and len(set(cands)) == len(cands)
+        ni = (p - 2) ** 2
+        for v, c in cands:
+            assert v in (1, 2) and c % 16 == 0 and 0 <= c <= 1024
+            if v == 2:
+                assert ni <= 256
+    assert any(v == 2 for v, _ in tune.candidates(16))
+    assert all(v == 1 for v, _ in tune.candidates(20))
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "sub" / "tune.json")
+    assert tune.load_cache(path) == {}
+    tune.save_cache(path, {"p16_fp64_L4096": {"setting": [2, 64], "ms": 5.0}})
+    assert os.path.exists(path)
+    assert tune.load_cache(path)["p16_fp64_L4096"]["setting"] == [2, 64]
