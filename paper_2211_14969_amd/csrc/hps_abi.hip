@@ -101,7 +101,7 @@ struct hps_batch {
   bool have_x = false;
   int *info = nullptr;      // [nleaf] internal per-leaf status
   int *conv = nullptr;      // [nleaf] refinement converged flags
-  double *norms = nullptr;  // [nleaf][8] refinement norms
+  double *norms = nullptr;  // [nleaf][kNormStride] refinement norms
   int *list = nullptr;      // [nleaf] leaves to redo in FP64
   int *count = nullptr;     // [2] length of list; leaves redone in FP64 by
                             //     the last condense
@@ -366,7 +366,7 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
         hipMalloc(&b->h, sizeof(double) * b->h_total) != hipSuccess ||
         hipMalloc(&b->info, sizeof(int) * b->nleaf) != hipSuccess ||
         hipMalloc(&b->conv, sizeof(int) * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->norms, sizeof(double) * 8 * b->nleaf) != hipSuccess ||
+        hipMalloc(&b->norms, sizeof(double) * hps::kNormStride * b->nleaf) != hipSuccess ||
         hipMalloc(&b->list, sizeof(int) * b->nleaf) != hipSuccess ||
         hipMalloc(&b->count, 2 * sizeof(int)) != hipSuccess)
       st = HPS_ERR_OOM;
@@ -450,7 +450,7 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
         // FP64 iterative refinement: residual -> stop test -> FP32 correction,
         // and one more residual after the last correction for the final test.
         int *conv = b->conv + gl;
-        double *nrm = b->norms + 8 * (size_t)gl;
+        double *nrm = b->norms + hps::kNormStride * (size_t)gl;
         const double tl = tol > 0.0 ? tol : 1e-10;
         HPS_TRY(hps::launch_fill_int(conv, n, 0, s));
         o.mode = hps::BACK_ACCUM;
@@ -466,10 +466,7 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
           }));
           if (it == nref) break;
           HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_fwdsolve(g, n, true, b->ws, b->piv, b->rstep, conv, s);
-          }));
-          HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_backsolve(g, n, true, b->ws, b->piv, b->rstep, o, s);
+            return hps::launch_refine_solve(g, n, b->ws, b->piv, b->rstep, o, s);
           }));
         }
         // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
@@ -566,7 +563,7 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
 
 hps_status hps_batch_set_tuning(hps_batch *b, int g, int factor_variant, int chunk_cols) {
   if (!b || g < 0 || g >= (int)b->groups.size()) return HPS_ERR_INVALID;
-  if (factor_variant < 0 || factor_variant > 2) return HPS_ERR_INVALID;
+  if (factor_variant < 0 || factor_variant > 3) return HPS_ERR_INVALID;
   if (chunk_cols < 0 || chunk_cols > 1024 || (chunk_cols & 15)) return HPS_ERR_INVALID;
   b->groups[g].tune_variant = factor_variant;
   b->groups[g].tune_ch = chunk_cols;

@@ -21,7 +21,8 @@ struct Geom {
   const double *a11, *a22, *c1, *c2, *k2b;  // [nleaf][p*p] or nullptr
   const double *D;                          // [p][p]  d/dt on [-1, 1]
   const double *D2;                         // [p][p]  D*D
-  int tune_variant;   // factorisation: 0 automatic, 1 one panel per pass, 2 panel pairs
+  int tune_variant;   // factorisation: 0 automatic, 1 one panel per pass, 2 panel pairs,
+                      // 3 register-resident (FP32, R <= 208)
   int tune_ch;        // column chunk of the U12 / trailing passes (0 automatic)
 };
 
@@ -50,12 +51,15 @@ struct BackOut {
   double *Xt;        // [nleaf][nb][ni]
   double *h;         // [nleaf][ni]   (nullptr when no f column)
   double *ui;        // [nleaf][ni]   (BACK_UI)
-  double *norms;     // [nleaf][8]: slot 5 receives ||dX||^2 (BACK_ACCUM)
+  double *norms;     // [nleaf][kNormStride]: slot 5 receives ||dX||^2 (BACK_ACCUM)
   const int *skip;   // [nleaf] leaves to leave untouched (nullptr = none)
   int mode;
 };
 
 constexpr int kInfoActive = 0x7fffffff;
+// refinement norms per leaf: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2,
+// 5 ||dX||^2 of the last correction, 6 relative size of the first correction
+constexpr int kNormStride = 8;
 
 // Launchers (hps_kernels.hip).  All enqueue on `s` and return hipError_t.
 // Factorisation of the work matrices; step 0 forms them from the operator
@@ -69,6 +73,10 @@ hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
 hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M,
                            const int *piv, const int *rstep, const int *skip,
                            hipStream_t s);
+// forward + back substitution of FP32 factors on the right-hand sides held in
+// the work matrix (the refinement residual), accumulating into o.Xt / o.h
+hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
+                               const int *rstep, const BackOut &o, hipStream_t s);
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip,
                            double *norms, hipStream_t s);

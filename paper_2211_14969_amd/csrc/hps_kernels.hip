@@ -707,8 +707,8 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256, 2) k_factor2(Geom g, T *M, int *piv, int *rstep,
+template <typename T, int MINB>
+__global__ void __launch_bounds__(256, MINB) k_factor2_t(Geom g, T *M, int *piv, int *rstep,
                                                     int *info, int CH, Sel sel, BuildSrc bs) {
   constexpr int NT = 256, NW = 4;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -917,6 +917,442 @@ __global__ void __launch_bounds__(256, 2) k_factor2(Geom g, T *M, int *piv, int 
 }
 
 // ---------------------------------------------------------------------------
+// Operator tables staged in LDS for one leaf: D, D^2 (p x p) and the
+// coefficient samples of the leaf (p x p each, absent ones NULL), so that
+// forming W reads no global memory per element.
+// ---------------------------------------------------------------------------
+struct StagedOp {
+  const double *D, *D2, *a11, *c1, *a22, *c2, *k2b;
+};
+
+__device__ __forceinline__ double opval_s(int p, const StagedOp &t, LeafScale sc, int i, int j,
+                                          int k, int l) {
+  const int n = i + p * j;
+  double v = 0.0;
+  if (l == j) {
+    const double a = t.a11 ? t.a11[n] : 1.0;
+    const double c = t.c1 ? t.c1[n] : 0.0;
+    v -= a * (sc.sx * sc.sx) * t.D2[i * p + k] + c * sc.sx * t.D[i * p + k];
+  }
+  if (k == i) {
+    const double a = t.a22 ? t.a22[n] : 1.0;
+    const double c = t.c2 ? t.c2[n] : 0.0;
+    v -= a * (sc.sy * sc.sy) * t.D2[j * p + l] + c * sc.sy * t.D[j * p + l];
+  }
+  if (k == i && l == j && t.k2b) v -= t.k2b[n];
+  return v;
+}
+
+// build_elem with the tables in LDS (condensation right-hand sides only)
+__device__ __forceinline__ double build_elem_s(const Geom &g, const StagedOp &t, LeafScale sc,
+                                               int leaf, const double *f, int r, int c) {
+  const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R;
+  if (r >= ni) return (c == r) ? 1.0 : 0.0;
+  const int i = r % m + 1, j = r / m + 1;
+  if (c < ni) return opval_s(p, t, sc, i, j, c % m + 1, c / m + 1);
+  if (c < R) return 0.0;
+  const int jr = c - R;
+  if (jr < nb) {
+    int k, l;
+    bnode(jr, m, p, k, l);
+    return opval_s(p, t, sc, i, j, k, l);
+  }
+  if (jr == nb && f) return f[(size_t)leaf * ni + r];
+  return 0.0;
+}
+
+// Wavefront maximum of a 32-bit key (DPP as in wave_max_u64); every lane
+// receives it.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xb1, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4e, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118, 0xf, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xa, 0xf, false));
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xc, 0xf, false));
+  return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// One column C of the FP32 single-wavefront panel of factor_rr.  Rows of a
+// lane: v[t][*] = row lane + 64t (R <= 256).  The pivot rule is that of
+// panel_column up to the key's resolution (the top 24 bits of the FP32
+// magnitude above the complemented row index: candidates within a relative
+// 2^-16 count as ties, the lowest row wins).  The pivot row is broadcast
+// through LDS and the multipliers use the reciprocal of the pivot.
+template <int C>
+__device__ __forceinline__ void rr_panel_column(float (&v)[4][16], unsigned &act, int lane, int k,
+                                                float *prb, int *pv, int *rst, int &zp) {
+  unsigned key = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if ((act >> t) & 1u) {
+      const unsigned kt = ((__float_as_uint(fabsf(v[t][C])) >> 7) << 8) | (unsigned)(255 - (lane + 64 * t));
+      key = max(key, kt);
+    }
+  }
+  key = wave_max_u32(key);
+  const int pr = 255 - (int)(key & 255u);
+  const int pt = pr >> 6, pl = pr & 63;
+  if (lane == pl) {
+    act &= ~(1u << pt);
+    // register pt selected by bit masks (a select of values, which the
+    // compiler would otherwise turn into an indexed, memory-backed access)
+    const unsigned m1 = 0u - (unsigned)(pt & 1), m2 = 0u - (unsigned)((pt >> 1) & 1);
+#pragma unroll
+    for (int cc = C; cc < 16; ++cc) {
+      const unsigned b0 = __float_as_uint(v[0][cc]), b1 = __float_as_uint(v[1][cc]);
+      const unsigned b2 = __float_as_uint(v[2][cc]), b3 = __float_as_uint(v[3][cc]);
+      const unsigned b01 = (b0 & ~m1) | (b1 & m1), b23 = (b2 & ~m1) | (b3 & m1);
+      prb[cc] = __uint_as_float((b01 & ~m2) | (b23 & m2));
+    }
+  }
+  wave_lds_fence<float>();
+  float pw[16];
+#pragma unroll
+  for (int cc = C; cc < 16; ++cc) pw[cc] = prb[cc];
+  const float pval = pw[C];
+  if (lane == 0) {
+    pv[C] = pr;
+    rst[pr] = k;
+    if (pval == 0.0f && zp == 0) zp = k * 16 + C + 1;
+  }
+  const float inv = pval != 0.0f ? __builtin_amdgcn_rcpf(pval) : 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if ((act >> t) & 1u) {
+      const float l = v[t][C] * inv;
+      v[t][C] = l;
+#pragma unroll
+      for (int cc = C + 1; cc < 16; ++cc) v[t][cc] = fmaf(-l, pw[cc], v[t][cc]);
+    }
+  }
+  wave_lds_fence<float>();
+}
+
+template <int... Cs>
+__device__ __forceinline__ void rr_panel_columns(float (&v)[4][16], unsigned &act, int lane, int k,
+                                                 float *prb, int *pv, int *rst, int &zp,
+                                                 std::integer_sequence<int, Cs...>) {
+  (rr_panel_column<Cs>(v, act, lane, k, prb, pv, rst, zp), ...);
+}
+
+// ---------------------------------------------------------------------------
+// factor_rr: the same factorisation with the whole FP32 work matrix held in
+// registers (R <= 208, i.e. p <= 16: 13 x 17 tiles, 226 KB per leaf, spread
+// over the register files of one CU), so that no trailing tile travels
+// through L2/HBM; one workgroup of NW wavefronts per leaf.  Wavefront w owns
+// the column tiles w, w + NW, ... (all row tiles of each), as FP32 values in
+// the FP64 MFMA accumulator order (lane l: column l%16, rows 4q + l/16).
+// Panel k is factored by the owner of column tile k with the
+// single-wavefront panel, into one of two LDS buffers, together with
+// L11^{-1}.  Step k then updates every column tile right of k: the 16 pivot
+// rows are gathered (the rows a lane holds are the same in every column
+// tile, so a per-lane mask of "my rows retired at step k" selects them),
+// U12 = L11^{-1} A12 is formed on MFMA and put back into the pivot rows, and
+// the active row tiles take C -= L21 U12, four row tiles at a time.  Look-
+// ahead: within step k the owner of column tile k+1 updates that tile
+// first and factors panel k+1 into the other buffer while the remaining
+// updates of step k proceed, so the serial panel overlaps the MFMA work.
+// (Rows retired by panel k+1 are still "after k" for step k: the update
+// mask is rstep > k.)  The result is the stored form of k_factor
+// (multipliers in the panel columns, U rows in the pivot rows, retire
+// steps), written to the work matrix once at the end.
+// ---------------------------------------------------------------------------
+template <int RT, int NW, int NS>
+__global__ void __launch_bounds__(64 * NW, 1) k_factor_rr(Geom g, float *M, int *piv, int *rstep,
+                                                          int *info, Sel sel, BuildSrc bs) {
+  constexpr int R = 16 * RT;
+  constexpr int NT = 64 * NW;
+  __shared__ float P[2][R * kPST];           // panels (double-buffered); build staging
+  __shared__ float Li[2][16 * kPST];         // L11^{-1} of each panel buffer
+  __shared__ float Ub[NW][17 * kPST];        // per wavefront: pivot rows, then U12 (+ trash row)
+  __shared__ float prb[16];                  // pivot row broadcast inside a panel
+  __shared__ int rst[R];
+  __shared__ int prow[R];                    // position of a pivot row in its panel's pv
+  __shared__ int pvs[2][16];
+  __shared__ int tileAct[2][RT], tilePiv[2][RT];
+  __shared__ int zeroPiv;
+  __shared__ double tab[7 * 256];            // D, D^2 and the leaf's coefficient samples (p <= 16)
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  const int CT = g.CT, p = g.p, pp = p * p, m = g.m, ni = g.ni, nb = g.nb;
+  const int lr = lane >> 4, lc = lane & 15;
+  float v[NS][RT][4];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[s][ti][q] = 0.0f;
+  {
+    // stage the tables, then build W one column tile at a time through LDS
+    auto stage = [&](const double *src, int slot, bool per_leaf) -> const double * {
+      if (!src) return nullptr;
+      const double *sp = per_leaf ? src + (size_t)leaf * pp : src;
+      for (int e = tid; e < pp; e += NT) tab[slot * 256 + e] = sp[e];
+      return tab + slot * 256;
+    };
+    StagedOp t;
+    t.D = stage(g.D, 0, false);
+    t.D2 = stage(g.D2, 1, false);
+    t.a11 = stage(g.a11, 2, true);
+    t.c1 = stage(g.c1, 3, true);
+    t.a22 = stage(g.a22, 4, true);
+    t.c2 = stage(g.c2, 5, true);
+    t.k2b = stage(g.k2b, 6, true);
+    __syncthreads();
+    const LeafScale sc = leaf_scale(g, leaf);
+    // this thread's column within a tile and first row; rows step by NT/16
+    constexpr int RSTEP = NT / 16;
+    const int cc = tid & 15, r0 = tid >> 4;
+    const int i0 = r0 % m + 1, j0 = r0 / m + 1;
+    float *P0 = P[0];
+    for (int J = 0; J < CT; ++J) {
+      const int c = 16 * J + cc;
+      int kind = 4, kc = 0, lcn = 0;   // 0 interior node, 2 boundary node, 3 f, 4 zero
+      if (c < ni) {
+        kind = 0;
+        kc = c % m + 1;
+        lcn = c / m + 1;
+      } else if (c >= R) {
+        const int jr = c - R;
+        if (jr < nb) {
+          kind = 2;
+          bnode(jr, m, p, kc, lcn);
+        } else if (jr == nb && bs.f) {
+          kind = 3;
+        }
+      }
+      int i = i0, jj = j0;
+      for (int r = r0; r < R; r += RSTEP) {
+        float val = 0.0f;
+        if (r >= ni) {
+          val = (c == r) ? 1.0f : 0.0f;
+        } else if (kind <= 2) {
+          val = (float)opval_s(p, t, sc, i, jj, kc, lcn);
+        } else if (kind == 3) {
+          val = (float)bs.f[(size_t)leaf * ni + r];
+        }
+        P0[r * kPST + cc] = val;
+        i += RSTEP;
+        while (i > m) {
+          i -= m;
+          ++jj;
+        }
+      }
+      __syncthreads();
+      if (wv == J % NW) {
+        const int sj = J / NW;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (s == sj) {
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) v[s][ti][q] = P0[(16 * ti + 4 * q + lr) * kPST + lc];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
+  int zp = 0;   // first zero pivot (1-based column) seen by this wavefront's panels
+  __syncthreads();
+
+  // k = -1 only factors panel 0; step k >= 0 updates with panel k and, in
+  // the wavefront owning column tile k+1, factors panel k+1 on the way.
+  for (int k = -1; k < RT; ++k) {
+    const int b = k & 1;
+    unsigned ta = 0, tp = 0;
+    unsigned long long pm = 0;
+    if (k >= 0) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        ta |= (unsigned)(tileAct[b][t] != 0) << t;
+        tp |= (unsigned)(tilePiv[b][t] != 0) << t;
+      }
+      ta = __builtin_amdgcn_readfirstlane(ta);
+      tp = __builtin_amdgcn_readfirstlane(tp);
+#pragma unroll
+      for (int ti = 0; ti < RT; ++ti) {
+        if ((tp >> ti) & 1u) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (rst[16 * ti + 4 * q + lr] == k) pm |= 1ull << (4 * ti + q);
+        }
+      }
+    }
+    const int kn = k + 1, sn = kn / NW;
+    const bool owner_next = kn < RT && wv == kn % NW;
+    const float *Pk = P[b];
+    const float *Lk = Li[b];
+    float *U = Ub[wv];
+    // pass 0: the next panel's column tile (its owner only), then that
+    // panel; pass 1: every other column tile right of k
+    for (int pass = 0; pass < 2; ++pass) {
+      if (k >= 0) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int j = wv + NW * s;
+          if (j >= CT || j <= k) continue;
+          if ((pass == 0) != (owner_next && s == sn)) continue;
+          // pivot rows into U (rows of other lanes go to the trash row 16)
+#pragma unroll
+          for (int ti = 0; ti < RT; ++ti) {
+            if ((tp >> ti) & 1u) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const bool isp = (pm >> (4 * ti + q)) & 1ull;
+                const int d = isp ? prow[16 * ti + 4 * q + lr] : 16;
+                U[d * kPST + lc] = v[s][ti][q];
+              }
+            }
+          }
+          wave_lds_fence<float>();
+          const d4 u = tri_apply<float>(Lk, U, kPST, 0, lane);
+          wave_lds_fence<float>();
+#pragma unroll
+          for (int q = 0; q < 4; ++q) U[(4 * q + lr) * kPST + lc] = (float)u[q];
+          wave_lds_fence<float>();
+#pragma unroll
+          for (int ti = 0; ti < RT; ++ti) {
+            if ((tp >> ti) & 1u) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const bool isp = (pm >> (4 * ti + q)) & 1ull;
+                const float w = U[(isp ? prow[16 * ti + 4 * q + lr] : 16) * kPST + lc];
+                v[s][ti][q] = isp ? w : v[s][ti][q];
+              }
+            }
+          }
+          float bop[4];
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) bop[kc] = U[(4 * kc + lr) * kPST + lc];
+          // C -= L21 U12 on the active row tiles, four independent tiles at a time
+#pragma unroll
+          for (int tg = 0; tg < (RT + 3) / 4; ++tg) {
+            if (!((ta >> (4 * tg)) & 0xfu)) continue;
+            constexpr int G = 4;
+            float a[G][4];
+            d4 c[G];
+#pragma unroll
+            for (int tt = 0; tt < G; ++tt) {
+              const int ti = 4 * tg + tt;
+              if (ti >= RT) continue;
+              const int ar = 16 * ti + lc;
+              const bool act = rst[ar] > k;
+#pragma unroll
+              for (int kc = 0; kc < 4; ++kc) a[tt][kc] = act ? -Pk[ar * kPST + 4 * kc + lr] : 0.0f;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) c[tt][q] = v[s][ti][q];
+            }
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+#pragma unroll
+              for (int tt = 0; tt < G; ++tt)
+                if (4 * tg + tt < RT) c[tt] = Mfma<float>::op(a[tt][kc], bop[kc], c[tt]);
+            }
+#pragma unroll
+            for (int tt = 0; tt < G; ++tt) {
+              const int ti = 4 * tg + tt;
+              if (ti >= RT) continue;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) v[s][ti][q] = (float)c[tt][q];
+            }
+          }
+          wave_lds_fence<float>();
+        }
+      }
+      if (pass == 0 && owner_next) {
+        // factor panel kn into buffer kn & 1
+        const int bn = kn & 1;
+        float *Pn = P[bn];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (s == sn) {
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) Pn[(16 * ti + 4 * q + lr) * kPST + lc] = v[s][ti][q];
+          }
+        }
+        wave_lds_fence<float>();
+        {
+          float pr[4][16];
+          unsigned act = 0;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = lane + 64 * t;
+            const bool in = r < R;
+            if (in && rst[r] == kInfoActive) act |= 1u << t;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) pr[t][c] = in ? Pn[r * kPST + c] : 0.0f;
+          }
+          rr_panel_columns(pr, act, lane, kn, prb, pvs[bn], rst, zp,
+                           std::make_integer_sequence<int, 16>());
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int r = lane + 64 * t;
+            if (r < R) {
+#pragma unroll
+              for (int c = 0; c < 16; ++c) Pn[r * kPST + c] = pr[t][c];
+            }
+          }
+        }
+        wave_lds_fence<float>();
+        linv16<float>(Pn, pvs[bn], Li[bn], lane);
+        if (lane < 16) {
+          prow[pvs[bn][lane]] = lane;
+          piv[(size_t)wi * R + kn * 16 + lane] = pvs[bn][lane];
+        }
+        for (int t = lane; t < RT; t += 64) {
+          int ac = 0, pc = 0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int st = rst[t * 16 + q];
+            ac |= (st == kInfoActive);
+            pc |= (st == kn);
+          }
+          tileAct[bn][t] = ac;
+          tilePiv[bn][t] = pc;
+        }
+        wave_lds_fence<float>();
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          if (s == sn) {
+#pragma unroll
+            for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) v[s][ti][q] = Pn[(16 * ti + 4 * q + lr) * kPST + lc];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  float *Ml = M + leaf_stride(g) * wi;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int j = wv + NW * s;
+    if (j >= CT) continue;
+#pragma unroll
+    for (int ti = 0; ti < RT; ++ti)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Ml[((size_t)(ti * CT + j) << 8) + q * 64 + lane] = v[s][ti][q];
+  }
+  for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
+  // the first zero pivot over all panels (each panel owner's lane 0 saw its own)
+  if (tid == 0) zeroPiv = INT_MAX;
+  __syncthreads();
+  if (lane == 0 && zp) atomicMin(&zeroPiv, zp);
+  __syncthreads();
+  if (tid == 0) info[leaf] = zeroPiv == INT_MAX ? 0 : zeroPiv;
+}
+
+// ---------------------------------------------------------------------------
 // forward replay of the stored L on fresh right-hand sides (refinement)
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
@@ -1058,7 +1494,7 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
     if (tid == 0) {
       double a = 0.0;
       for (int w = 0; w < NW; ++w) a += red[w];
-      o.norms[8 * (size_t)leaf + 5] = a;
+      o.norms[kNormStride * (size_t)leaf + 5] = a;
     }
   }
 }
@@ -1066,22 +1502,24 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
 // ---------------------------------------------------------------------------
 // FP64 refinement residual  r = A_ib - A_ii X  (and f_i - A_ii h), applied
 // through the tensor structure of the collocation operator: each interior
-// row couples only to its own x1-line and x2-line of nodes.  The residual is
-// written in FP32 into the right-hand-side columns of the work matrix for the
-// correction solve, and the squared Frobenius norms of r, X, A_ii and
-// [A_ib f_i] are stored per leaf for the backward-error stop test.
+// row couples only to its own x1-line and x2-line of nodes.  One workgroup
+// per leaf; a thread owns one row and keeps its coefficients in
+// registers; CW columns of [X h] at a time are staged in LDS (coalesced
+// reads of Xt); each line weight is formed once per row and chunk and used
+// for all CW columns.  The residual is written in FP32 into the
+// right-hand-side columns of the work matrix for the correction solve (zero
+// in the padding rows), and the squared Frobenius norms of r and X are
+// stored per leaf for the stop test.
 // ---------------------------------------------------------------------------
-constexpr int kResRows = 4;    // rows per thread: R <= 4 * 256
-constexpr int kResCols = 8;    // columns of [X h] staged per pass
-
-__global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const double *Xt,
+template <int NT, int CW>
+__global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const double *Xt,
                                                   const double *h, const double *f,
-                                                  const int *skip, double *norms, int RC) {
+                                                  const int *skip, double *norms) {
   extern __shared__ __align__(16) unsigned char smem[];
   double *sD = (double *)smem;               // [p*p]
   double *sD2 = sD + g.p * g.p;              // [p*p]
-  double *xs = sD2 + g.p * g.p;              // [RC][ni] staged columns of [X h]
-  __shared__ double red[4][4];
+  double *xs = sD2 + g.p * g.p;              // [CW][ni] staged columns of [X h]
+  __shared__ double red[NT / 64][2];
   const int leaf = blockIdx.x;
   if (skip && skip[leaf]) return;
   stage_tables(g, sD, sD2);
@@ -1090,136 +1528,84 @@ __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const doub
   const size_t nbase = (size_t)leaf * p * p;
   float *Ml = M32 + leaf_stride(g) * leaf;
   const int ncol = (h && f) ? nb + 1 : nb;
-  // per-row operator data in registers: the x1-line and x2-line weights
-  // come from D and D^2 scaled by the row's coefficients
-  double ax2[kResRows], ax1[kResRows], ay2[kResRows], ay1[kResRows], kb[kResRows];
-  double bw[kResRows][4], fr[kResRows];
-  int ri[kResRows], rj[kResRows];
-  double nr = 0.0, nx = 0.0, na = 0.0, nbb = 0.0;
-#pragma unroll
-  for (int t = 0; t < kResRows; ++t) {
-    const int r = threadIdx.x + 256 * t;
-    ri[t] = 0;
-    rj[t] = 0;
-    ax2[t] = ax1[t] = ay2[t] = ay1[t] = kb[t] = fr[t] = 0.0;
-    bw[t][0] = bw[t][1] = bw[t][2] = bw[t][3] = 0.0;
-    if (r < ni) {
-      const int i = r % m + 1, j = r / m + 1;
-      ri[t] = i;
-      rj[t] = j;
-      const size_t n = nbase + i + (size_t)p * j;
-      const double a11 = g.a11 ? g.a11[n] : 1.0, c1 = g.c1 ? g.c1[n] : 0.0;
-      const double a22 = g.a22 ? g.a22[n] : 1.0, c2 = g.c2 ? g.c2[n] : 0.0;
-      kb[t] = g.k2b ? g.k2b[n] : 0.0;
-      ax2[t] = a11 * sc.sx * sc.sx;
-      ax1[t] = c1 * sc.sx;
-      ay2[t] = a22 * sc.sy * sc.sy;
-      ay1[t] = c2 * sc.sy;
-      fr[t] = (h && f) ? f[(size_t)leaf * ni + r] : 0.0;
-    }
+  const int r = threadIdx.x;   // this thread's row (NT >= R)
+  int i = 0, j = 0;
+  double ax2 = 0.0, ax1 = 0.0, ay2 = 0.0, ay1 = 0.0, kb = 0.0;
+  if (r < ni) {
+    i = r % m + 1;
+    j = r / m + 1;
+    const size_t n = nbase + i + (size_t)p * j;
+    ax2 = (g.a11 ? g.a11[n] : 1.0) * sc.sx * sc.sx;
+    ax1 = (g.c1 ? g.c1[n] : 0.0) * sc.sx;
+    ay2 = (g.a22 ? g.a22[n] : 1.0) * sc.sy * sc.sy;
+    ay1 = (g.c2 ? g.c2[n] : 0.0) * sc.sy;
+    kb = g.k2b ? g.k2b[n] : 0.0;
   }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < kResRows; ++t) {
-    const int r = threadIdx.x + 256 * t;
-    if (r < ni) {
-      const int i = ri[t], j = rj[t];
-      // A_ib row: the four edge nodes on the row's two grid lines (W, E, S, N)
-      bw[t][0] = -(ax2[t] * sD2[i * p + 0] + ax1[t] * sD[i * p + 0]);
-      bw[t][1] = -(ax2[t] * sD2[i * p + p - 1] + ax1[t] * sD[i * p + p - 1]);
-      bw[t][2] = -(ay2[t] * sD2[j * p + 0] + ay1[t] * sD[j * p + 0]);
-      bw[t][3] = -(ay2[t] * sD2[j * p + p - 1] + ay1[t] * sD[j * p + p - 1]);
-      // squared norm of row r of A_ii (the diagonal joins both lines and k2b)
-      double diag = -kb[t];
-      for (int k = 1; k <= m; ++k) {
-        const double v = -(ax2[t] * sD2[i * p + k] + ax1[t] * sD[i * p + k]);
-        if (k == i) diag += v; else na += v * v;
-      }
-      for (int l = 1; l <= m; ++l) {
-        const double v = -(ay2[t] * sD2[j * p + l] + ay1[t] * sD[j * p + l]);
-        if (l == j) diag += v; else na += v * v;
-      }
-      na += diag * diag;
-      nbb += bw[t][0] * bw[t][0] + bw[t][1] * bw[t][1] + bw[t][2] * bw[t][2] +
-             bw[t][3] * bw[t][3] + fr[t] * fr[t];
-    }
-  }
-  for (int c0 = 0; c0 < ncol; c0 += RC) {
-    const int cw = min(RC, ncol - c0);
+  double nr = 0.0, nx = 0.0;
+  for (int c0 = 0; c0 < ncol; c0 += CW) {
+    const int cw = min(CW, ncol - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < cw * ni; e += blockDim.x) {
+    for (int e = threadIdx.x; e < cw * ni; e += NT) {
       const int c = e / ni, i = e - c * ni, col = c0 + c;
-      xs[c * ni + i] = (col < nb) ? Xt[((size_t)leaf * nb + col) * ni + i]
-                                  : h[(size_t)leaf * ni + i];
+      xs[c * ni + i] = (col < nb) ? Xt[((size_t)leaf * nb + col) * ni + i] : h[(size_t)leaf * ni + i];
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < kResRows; ++t) {
-      const int r = threadIdx.x + 256 * t;
-      if (r >= R) continue;
-      if (r >= ni) {
+    if (r >= ni) {
+      if (r < R)
         for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = 0.0f;
-        continue;
-      }
-      const int i = ri[t], j = rj[t];
-      double acc[kResCols];
+      continue;
+    }
+    // -(A_ii x) = k2b x + sum over both lines of (a d2 + c d1) x
+    double acc[CW];
 #pragma unroll
-      for (int c = 0; c < kResCols; ++c) acc[c] = c < cw ? -kb[t] * xs[c * ni + r] : 0.0;
-      for (int k = 1; k <= m; ++k) {
-        const double wgt = ax2[t] * sD2[i * p + k] + ax1[t] * sD[i * p + k];
-        const int xi = (k - 1) + m * (j - 1);
+    for (int c = 0; c < CW; ++c) acc[c] = c < cw ? kb * xs[c * ni + r] : 0.0;
+    for (int k = 1; k <= m; ++k) {
+      const double wx = ax2 * sD2[i * p + k] + ax1 * sD[i * p + k];
+      const double wy = ay2 * sD2[j * p + k] + ay1 * sD[j * p + k];
+      const int xa = (k - 1) + m * (j - 1), ya = (i - 1) + m * (k - 1);
 #pragma unroll
-        for (int c = 0; c < kResCols; ++c)
-          if (c < cw) acc[c] -= wgt * xs[c * ni + xi];
-      }
-      for (int l = 1; l <= m; ++l) {
-        const double wgt = ay2[t] * sD2[j * p + l] + ay1[t] * sD[j * p + l];
-        const int xi = (i - 1) + m * (l - 1);
-#pragma unroll
-        for (int c = 0; c < kResCols; ++c)
-          if (c < cw) acc[c] -= wgt * xs[c * ni + xi];
-      }
-#pragma unroll
-      for (int c = 0; c < kResCols; ++c) {
-        if (c >= cw) continue;
-        const int col = c0 + c;
-        double bval;
-        if (col == nb) {
-          bval = fr[t];
-        } else {
-          bval = 0.0;
-          if (col == j - 1) bval = bw[t][0];
-          else if (col == m + j - 1) bval = bw[t][1];
-          else if (col == 2 * m + i - 1) bval = bw[t][2];
-          else if (col == 3 * m + i - 1) bval = bw[t][3];
-        }
-        const double res = bval - acc[c];
-        nr += res * res;
-        nx += xs[c * ni + r] * xs[c * ni + r];
-        Ml[tix<float>(r, R + col, CT)] = (float)res;
+      for (int c = 0; c < CW; ++c) {
+        if (c < cw) acc[c] += wx * xs[c * ni + xa] + wy * xs[c * ni + ya];
       }
     }
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      if (c >= cw) continue;
+      const int col = c0 + c;
+      double bval = 0.0;   // entry of [A_ib f] in this row
+      if (col == nb) {
+        bval = f[(size_t)leaf * ni + r];
+      } else if (col == j - 1) {
+        bval = -(ax2 * sD2[i * p] + ax1 * sD[i * p]);
+      } else if (col == m + j - 1) {
+        bval = -(ax2 * sD2[i * p + p - 1] + ax1 * sD[i * p + p - 1]);
+      } else if (col == 2 * m + i - 1) {
+        bval = -(ay2 * sD2[j * p] + ay1 * sD[j * p]);
+      } else if (col == 3 * m + i - 1) {
+        bval = -(ay2 * sD2[j * p + p - 1] + ay1 * sD[j * p + p - 1]);
+      }
+      const double res = bval + acc[c];
+      const double x = xs[c * ni + r];
+      nr += res * res;
+      nx += x * x;
+      Ml[tix<float>(r, R + col, CT)] = (float)res;
+    }
   }
-  // block reduction of the four sums
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     nr += __shfl_xor(nr, off);
     nx += __shfl_xor(nx, off);
-    na += __shfl_xor(na, off);
-    nbb += __shfl_xor(nbb, off);
   }
   if (lane == 0) {
     red[wv][0] = nr;
     red[wv][1] = nx;
-    red[wv][2] = na;
-    red[wv][3] = nbb;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < 2) {
     double a = 0.0;
-    for (int w = 0; w < 4; ++w) a += red[w][threadIdx.x];
-    norms[8 * (size_t)leaf + threadIdx.x] = a;
+    for (int w = 0; w < NT / 64; ++w) a += red[w][threadIdx.x];
+    norms[kNormStride * (size_t)leaf + threadIdx.x] = a;
   }
 }
 
@@ -1235,13 +1621,14 @@ __global__ void __launch_bounds__(256) k_residual(Geom g, float *M32, const doub
 // cond(A_ii) 2^-53, lies above tol) never passes.  An exactly zero residual
 // passes; tol >= 1 passes on the final check without a test.  On the final
 // check a leaf that did not pass is flagged -1.
-// norms[8l + ...]: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2, 5 ||dX||^2 of
-// the last correction, 6 the relative size of the first correction.
+// norms[kNormStride l + ...]: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2,
+// 5 ||dX||^2 of the last correction, 6 the relative size of the first
+// correction.
 __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
                             int it, int last) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaf || conv[l]) return;
-  double *n = norms + 8 * (size_t)l;
+  double *n = norms + kNormStride * (size_t)l;
   bool ok = n[0] == 0.0 || (tol >= 1.0 && last);
   if (it == 1) n[6] = n[1] > 0.0 ? sqrt(n[5] / n[1]) : 1.0;
   if (!ok && tol < 1.0 && it > 0 && n[4] > 0.0) {
@@ -1462,6 +1849,7 @@ int pick_ch(const Geom &g) {
   return 0;
 }
 
+
 template <typename T>
 size_t solve_lds(const Geom &g) {
   const int NRC = g.CT * 16 - g.R;
@@ -1531,17 +1919,69 @@ hipError_t launch_factor2(const Geom &g, int nleaf, T *M, int *piv, int *rstep, 
   const int ch = pick_ch2<T>(g);
   if (!ch) return hipErrorInvalidValue;
   const size_t lds = factor2_lds<T>(g, ch);
-  hipError_t e = set_lds(k_factor2<T>, lds);
+  if constexpr (std::is_same<T, float>::value) {
+    if (3 * lds <= kLdsLimit) {
+    hipError_t e = set_lds(k_factor2_t<T, 3>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_factor2_t<T, 3>), dim3(nleaf), dim3(256), lds, s, g, M, piv, rstep, info,
+                       ch, sel, bs);
+    return hipGetLastError();
+    }
+  }
+  hipError_t e = set_lds(k_factor2_t<T, 2>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_factor2<T>, dim3(nleaf), dim3(256), lds, s, g, M, piv, rstep, info, ch, sel,
-                     bs);
+  hipLaunchKernelGGL((k_factor2_t<T, 2>), dim3(nleaf), dim3(256), lds, s, g, M, piv, rstep, info,
+                     ch, sel, bs);
   return hipGetLastError();
+}
+
+template <int RT, int NW, int NS>
+hipError_t launch_rr(const Geom &g, int nleaf, float *M, int *piv, int *rstep, int *info,
+                     const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  if (g.CT > NW * NS) return hipErrorNotSupported;
+  hipLaunchKernelGGL((k_factor_rr<RT, NW, NS>), dim3(nleaf), dim3(64 * NW), 0, s, g, M, piv, rstep,
+                     info, sel, bs);
+  return hipGetLastError();
+}
+
+// Register-resident factorisation for the FP32 work matrices it covers
+// (R <= 208); hipErrorNotSupported otherwise.  The (RT, wavefronts, column
+// tiles per wavefront) instances cover p = 4 ... 16 with every right-hand
+// side count the library uses.
+hipError_t launch_factor_rr(const Geom &g, int nleaf, float *M, int *piv, int *rstep, int *info,
+                            const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  switch (g.RT) {
+    case 1: return launch_rr<1, 4, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 2: return launch_rr<2, 4, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 3: return launch_rr<3, 4, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 4: return launch_rr<4, 4, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 6: return launch_rr<6, 8, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 7: return launch_rr<7, 8, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 8: return launch_rr<8, 8, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 9: return launch_rr<9, 8, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 11: return launch_rr<11, 8, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    case 13: return launch_rr<13, 4, 5>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    default: return hipErrorNotSupported;
+  }
+}
+
+// HPS_FACTOR_RR=0 turns the register-resident factorisation off.
+bool factor_rr_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("HPS_FACTOR_RR");
+    return !(v && v[0] == '0');
+  }();
+  return on;
 }
 
 hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv, int *rstep,
                          int *info, int mode, const double *f, const double *ub, hipStream_t s,
                          const Sel &sel) {
   const BuildSrc bs{mode, f, ub};
+  if (fp32 && g.tune_variant == 3 && factor_rr_enabled()) {
+    const hipError_t e = launch_factor_rr(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
+    if (e != hipErrorNotSupported) return e;
+  }
   const bool pairs = g.R <= 256 && g.tune_variant != 1 && factor_pairs_enabled();
   if (pairs) {
     if (fp32) return launch_factor2<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
@@ -1581,6 +2021,27 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
   return hipGetLastError();
 }
 
+
+template <int NT, int CW>
+hipError_t launch_residual_t(const Geom &g, int nleaf, float *M32, const double *Xt,
+                             const double *h, const double *f, const int *skip, double *norms,
+                             hipStream_t s) {
+  if (g.R > NT) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (2 * (size_t)g.p * g.p + (size_t)CW * g.ni);
+  hipError_t e = set_lds(k_residual<NT, CW>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_residual<NT, CW>), dim3(nleaf), dim3(NT), lds, s, g, M32, Xt, h, f, skip,
+                     norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
+                           const double *h, const double *f, const int *skip, double *norms,
+                           hipStream_t s) {
+  if (g.R <= 256) return launch_residual_t<256, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
+  return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
+}
+
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
   if (fp32) {
@@ -1617,17 +2078,12 @@ hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M, const i
   return hipGetLastError();
 }
 
-hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
-                           const double *h, const double *f, const int *skip, double *norms,
-                           hipStream_t s) {
-  // columns staged per pass: as many as fit 48 KiB, at most 16
-  const int RC = kResCols;
-  const size_t lds = sizeof(double) * (2 * (size_t)g.p * g.p + (size_t)RC * g.ni);
-  hipError_t e = set_lds(k_residual, lds);
+hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
+                               const int *rstep, const BackOut &o, hipStream_t s) {
+
+  const hipError_t e = launch_fwdsolve(g, nleaf, true, M, piv, rstep, o.skip, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual, dim3(nleaf), dim3(256), lds, s, g, M32, Xt, h, f, skip, norms,
-                     RC);
-  return hipGetLastError();
+  return launch_backsolve(g, nleaf, true, M, piv, rstep, o, s);
 }
 
 hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info, int it,

@@ -2,8 +2,8 @@
 
 For every order group of a batch it times the candidate settings of
 `hps_batch_set_tuning` -- the factorisation variant (one 16-column panel per
-trailing pass, or panels in pairs) and the column chunk of the U12 / trailing
-passes -- on a batch of that group's own leaves, keeps the fastest, applies
+trailing pass, panels in pairs, or for FP32 and p <= 16 the work matrix held
+in registers) and the column chunk of the U12 / trailing passes -- on a batch of that group's own leaves, keeps the fastest, applies
 it to the batch, and remembers it in a JSON cache keyed by
 ``p<order>_<precision>_L<leaf-count bucket>``.  Timing uses the library's
 per-phase HIP events (`hps_ctx_phase_times`).
@@ -31,13 +31,18 @@ def cache_key(p: int, prec: int, nleaf: int) -> str:
     return f"p{p}_{'fp64' if prec == hps.HPS_FP64 else 'fp32r'}_L{bucket(nleaf)}"
 
 
-def candidates(p: int) -> List[Tuple[int, int]]:
-    """(variant, chunk_cols) pairs worth timing for order p."""
+def candidates(p: int, prec: int = hps.HPS_FP64) -> List[Tuple[int, int]]:
+    """(variant, chunk_cols) pairs worth timing for order p: the streaming
+    variants over their column chunks, and for FP32 work matrices of at most
+    208 rows the register-resident variant (which has no chunk)."""
     ni, nb = (p - 2) ** 2, 4 * (p - 2)
     cols = ((ni + 15) // 16) * 16 + ((nb + 1 + 15) // 16) * 16
     chunks = [c for c in (32, 64, 128, 256, 512) if c < cols] + [0]
     variants = [1, 2] if ni <= 256 else [1]
-    return [(v, c) for v in variants for c in chunks]
+    out = [(v, c) for v in variants for c in chunks]
+    if prec == hps.HPS_FP32_REFINE and ((ni + 15) // 16) * 16 <= 208:
+        out.append((3, 0))
+    return out
 
 
 def load_cache(path: Optional[str]) -> Dict[str, list]:
@@ -98,7 +103,7 @@ def tune_batch(lb, prec: int = hps.HPS_FP64, max_refine: int = 1, reps: int = 2,
                            exact=prob.exact, f=prob.f, meta=prob.meta)
         sub = LeafBatch([prob])
         timings = {}
-        for setting in candidates(G.p):
+        for setting in candidates(G.p, prec):
             timings[setting] = _time_setting(sub, prec, max_refine, setting, reps)
         sub.close()
         best = min(timings, key=timings.get)

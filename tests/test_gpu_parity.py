@@ -118,6 +118,39 @@ def test_condense_fp32_refine_orders(torch, p):
     _check_condense(torch, _small(p, 3), hps.HPS_FP32_REFINE, TOL_MIXED)
 
 
+@pytest.mark.parametrize("p", [o for o in ORDERS if o <= 16])
+def test_condense_fp32_register_resident(torch, p):
+    """The register-resident FP32 factorisation (tuning variant 3) meets the
+    same bar as the streaming one, with the f column present too."""
+    _say(f"condense fp32 register-resident p={p}")
+    prob = _small(p, 3)
+    B = _batch([prob])
+    hps.hps_batch_set_tuning(B.batch, 0, 3, 0)
+    S, w, info, st = B.condense(prec=hps.HPS_FP32_REFINE, max_refine=3, sync=True)
+    assert st == hps.HPS_OK and bool((info == 0).all())
+    nb = 4 * (p - 2)
+    Sg = S.view(prob.nleaf, nb, nb).cpu().numpy()
+    for t in range(prob.nleaf):
+        bl, c = oracle_leaf(prob, t)
+        assert relerr(Sg[t], c.S) <= leaf_bar(bl.Aii, TOL_MIXED), t
+    B.close()
+    fp = _forced_problem(p if p >= 6 else 6)
+    B = _batch([fp])
+    hps.hps_batch_set_tuning(B.batch, 0, 3, 0)
+    f = B.interior_f()
+    S, w, info, st = B.condense(prec=hps.HPS_FP32_REFINE, f=f, max_refine=3, sync=True)
+    assert st == hps.HPS_OK
+    nb, ni = 4 * (fp.p - 2), (fp.p - 2) ** 2
+    _, h = B.export()
+    Sg, wg, hg = (S.view(-1, nb, nb).cpu().numpy(), w.view(-1, nb).cpu().numpy(),
+                  h.view(-1, ni).cpu().numpy())
+    for t in range(fp.nleaf):
+        bl, c = oracle_leaf(fp, t, oracle_interior_f(fp, t))
+        bar = leaf_bar(bl.Aii, TOL_MIXED)
+        assert relerr(Sg[t], c.S) <= bar and relerr(wg[t], c.w) <= bar and relerr(hg[t], c.h) <= bar
+    B.close()
+
+
 @pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
 def test_annulus_variable_coefficients(torch, prec):
     _say(f"annulus prec={prec}")

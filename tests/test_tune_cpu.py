@@ -24,6 +24,14 @@ def test_candidates_respect_kernel_limits():
     assert all(v == 1 for v, _ in tune.candidates(20))
 
 
+def test_register_resident_candidate_only_for_small_fp32():
+    for p in range(4, 33):
+        R = ((p - 2) ** 2 + 15) // 16 * 16
+        has = (3, 0) in tune.candidates(p, hps.HPS_FP32_REFINE)
+        assert has == (R <= 208), p
+        assert all(v != 3 for v, _ in tune.candidates(p, hps.HPS_FP64))
+
+
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "sub" / "tune.json")
     assert tune.load_cache(path) == {}
