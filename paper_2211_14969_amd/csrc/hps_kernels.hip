@@ -1367,12 +1367,15 @@ __global__ void __launch_bounds__(NT) k_fwdsolve(Geom g, T *M, const int *piv,
   T *Lt = Y + 16 * YST;             // [16][kPST]
   int *rst = (int *)(Lt + 16 * kPST);
   int *tileAny = rst + R;
-  int *pv = tileAny + RT;
+  int *pva = tileAny + RT;          // [R] all pivots of the leaf
   T *Ml = M + leaf_stride(g) * leaf;
-  for (int r = tid; r < R; r += NT) rst[r] = rstep[(size_t)leaf * R + r];
+  for (int r = tid; r < R; r += NT) {
+    rst[r] = rstep[(size_t)leaf * R + r];
+    pva[r] = piv[(size_t)leaf * R + r];
+  }
+  __syncthreads();
   for (int k = 0; k < RT; ++k) {
-    if (tid < 16) pv[tid] = piv[(size_t)leaf * R + k * 16 + tid];
-    __syncthreads();
+    const int *pv = pva + 16 * k;
     for (int e = tid; e < 256; e += NT) {
       const int s = e >> 4, q = e & 15;
       Lt[s * kPST + q] = Ml[tix<T>(pv[s], k * 16 + q, CT)];
@@ -1424,18 +1427,24 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
   double *red = (double *)smem;     // [NW]
   T *Y = (T *)(red + NW);           // [16][YST]
   T *Ut = Y + 16 * YST;             // [16][kPST]
-  int *rst = (int *)(Ut + 16 * kPST);
+  T *Ud = Ut + 16 * kPST;           // [16] reciprocals of the diagonal of U11
+  int *rst = (int *)(Ud + 16);
   int *tileAny = rst + R;
-  int *pv = tileAny + RT;
+  int *pva = tileAny + RT;          // [R] all pivots of the leaf
   T *Ml = M + leaf_stride(g) * wi;
   double nd = 0.0;
-  for (int r = tid; r < R; r += NT) rst[r] = rstep[(size_t)wi * R + r];
+  for (int r = tid; r < R; r += NT) {
+    rst[r] = rstep[(size_t)wi * R + r];
+    pva[r] = piv[(size_t)wi * R + r];
+  }
+  __syncthreads();
   for (int k = RT - 1; k >= 0; --k) {
-    if (tid < 16) pv[tid] = piv[(size_t)wi * R + k * 16 + tid];
-    __syncthreads();
+    const int *pv = pva + 16 * k;
     for (int e = tid; e < 256; e += NT) {
       const int s = e >> 4, q = e & 15;
-      Ut[s * kPST + q] = Ml[tix<T>(pv[s], k * 16 + q, CT)];
+      const T u = Ml[tix<T>(pv[s], k * 16 + q, CT)];
+      Ut[s * kPST + q] = u;
+      if (q == s) Ud[s] = T(1) / u;
     }
     for (int e = tid; e < 16 * NRC; e += NT) {
       const int s = e / NRC, jr = e - s * NRC;
@@ -1454,7 +1463,7 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
         T acc = Y[s * YST + jr];
 #pragma unroll
         for (int q = s + 1; q < 16; ++q) acc -= Ut[s * kPST + q] * x[q];
-        x[s] = acc / Ut[s * kPST + s];
+        x[s] = acc * Ud[s];
       }
 #pragma unroll
       for (int s = 0; s < 16; ++s) Y[s * YST + jr] = x[s];
@@ -1854,8 +1863,8 @@ template <typename T>
 size_t solve_lds(const Geom &g) {
   const int NRC = g.CT * 16 - g.R;
   size_t b = sizeof(double) * (kSolveNT / 64);
-  b += sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST);
-  b += sizeof(int) * ((size_t)g.R + g.RT + 16);
+  b += sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST + 16);
+  b += sizeof(int) * (2 * (size_t)g.R + g.RT);
   return b;
 }
 
