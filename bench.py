@@ -6,6 +6,10 @@ collocation operator on the device, factor A_ii, solve for X = A_ii^{-1} A_ib
 and form S = A_bb - A_bi X (plus the FP64 refinement of X in the mixed
 precision mode).  Inputs (leaf boxes, coefficient samples) are resident in
 HBM before the timed region; nothing is copied to or from the host inside it.
+For the uneven eight-problem batch the step is the replay of one condense
+captured in a HIP graph, after the autotuner has picked the factorisation
+variant per order.  Recovery u_i = h - X u_b is timed separately against the
+HBM roofline.
 
 Workload: the unit square split into 64 x 64 leaves of order p = 16,
 kappa = 100, b(x) = 1 - 0.5 exp(-|x - (0.5, 0.5)|^2 / 0.05), in FP64.  The
@@ -83,23 +87,53 @@ def cpu_baseline(problem, seconds: float):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def recover_timing(B, steps: int):
+    """Time hps_leaf_recover (stored X) on the condensed batch: u_i = h - X u_b
+    per leaf.  HBM-bound: reads X (8 ni nb bytes per leaf) and u_b, writes u_i."""
+    import torch
+    from paper_2211_14969_amd import hps
+    ub = torch.randn(B.nb_total, dtype=torch.float64, device="cuda")
+    ui = torch.empty(B.ni_total, dtype=torch.float64, device="cuda")
+    hps.hps_leaf_recover(B.batch, ub, None, ui, 0)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        hps.hps_leaf_recover(B.batch, ub, None, ui, 0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nbytes = sum(8.0 * G.nleaf * (G.ni * G.nb + G.nb + G.ni) for G in B.groups)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"ms": ms, "leaves_per_s": B.nleaf / (ms * 1e-3), "bytes": nbytes, "GB_per_s": gbs,
+            "frac_hbm_peak": gbs / 8000.0, "bound": "hbm"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=("fp64", "fp32"), default="fp64",
-                    help="precision of the timed path (fp32 = FP32 + FP64 refinement)")
-    ap.add_argument("--max-refine", type=int, default=1)
+    ap.add_argument("--prec", choices=("fp64", "fp32"), default=None,
+                    help="precision of the timed path (fp32 = FP32 + FP64 refinement); "
+                         "default fp64, fp32 for the uneven batch")
+    ap.add_argument("--max-refine", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the FP32+refinement comparison run")
+                    help="skip the run of the other precision on the same batch")
+    ap.add_argument("--no-recover", action="store_true", help="skip the recovery timing")
     ap.add_argument("--workload", default="bump",
                     choices=("bump", "tiny", "bumps", "annulus", "uneven"),
                     help="bump: 64x64 leaves p=16 (default, the headline configuration); "
                          "tiny: 4x4 p=8; bumps: 32x32 p=32; annulus: 128x16 p=20; "
                          "uneven: the eight-problem batch p=8..32 in one batch")
+    ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
+                    help="time replays of one condense captured in a HIP graph "
+                         "(auto: on for the uneven batch)")
+    ap.add_argument("--tune", choices=("auto", "on", "off"), default="auto",
+                    help="autotune every order group before timing (auto: on for the uneven batch)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM traffic counters against a known byte count)")
@@ -128,6 +162,14 @@ def main() -> int:
         print(json.dumps({"copy_mib": args.copy_mib, "copies": 3}))
         return 0
     hps.load()
+    uneven = args.workload == "uneven"
+    prec_name = args.prec or ("fp32" if uneven else "fp64")
+    use_graph = args.graph == "on" or (args.graph == "auto" and uneven)
+    use_tune = args.tune == "on" or (args.tune == "auto" and uneven)
+    if use_graph:
+        # capture needs a stream other than the legacy default one; the
+        # library context binds to the current stream when the batch is built
+        torch.cuda.set_stream(torch.cuda.Stream())
     probs = {"bump": lambda: [inputs.single_bump()], "tiny": lambda: [inputs.tiny()],
              "bumps": lambda: [inputs.multi_bump()], "annulus": lambda: [inputs.annulus()],
              "uneven": lambda: inputs.uneven_batch()}[args.workload]()
@@ -137,28 +179,41 @@ def main() -> int:
           flush=True)
     B = LeafBatch(probs)
     S, w, info = B.alloc_outputs()
-    prec = hps.HPS_FP64 if args.prec == "fp64" else hps.HPS_FP32_REFINE
+    prec = hps.HPS_FP64 if prec_name == "fp64" else hps.HPS_FP32_REFINE
+    tuned = None
+    if use_tune:
+        from paper_2211_14969_amd import tune
+        tuned = tune.tune_batch(B, prec=prec, max_refine=args.max_refine, reps=1, cache_path=None)
+        tuned = {B.groups[g].p: list(r["setting"]) for g, r in tuned.items()}
+        print(f"# tuned (variant, chunk) per order: {tuned}", file=sys.stderr, flush=True)
 
-    def step(pr=prec, S_=S):
+    def condense(pr=prec, S_=S):
         hps.hps_leaf_condense(B.batch, pr, 0.0, args.max_refine, None, S_, w, info, 0)
 
-    for _ in range(args.warmup):
-        step()
+    for _ in range(max(args.warmup, 1)):
+        condense()
     torch.cuda.synchronize()
     st = hps.hps_leaf_condense(B.batch, prec, 0.0, args.max_refine, None, S, w, info, hps.HPS_SYNC)
     print(f"# warmup done, status {st}", file=sys.stderr, flush=True)
+    step = condense
+    if use_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=torch.cuda.current_stream()):
+            condense()
+        torch.cuda.synchronize()
+        step = graph.replay
 
-    hps.hps_ctx_set_timing(B.ctx, True)
+    hps.hps_ctx_set_timing(B.ctx, not use_graph)
     hps.hps_ctx_phase_times(B.ctx)          # reset
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         step()
-    ev1.record()
+        evs[i + 1].record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    per = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
+    ms = evs[0].elapsed_time(evs[-1]) / args.steps
     phases = hps.hps_ctx_phase_times(B.ctx)
     hps.hps_ctx_set_timing(B.ctx, False)
     bad = int((info != 0).sum().item())
@@ -166,12 +221,8 @@ def main() -> int:
 
     fl = {k: sum(algorithmic_flops(q.p)[k] * q.nleaf for q in probs) / L
           for k in ("factor", "backsolve", "schur", "total")}
-    f_ms, f_n = phases["factor"]
-    t_factor = f_ms / args.steps          # ms of factorisation launches per step
-    launch_ms = f_ms / max(f_n, 1)        # average duration of one launch
-    dtype = "f64" if args.prec == "fp64" else "f32+f64"
-    peak = PEAK_TFLOPS["fp64" if args.prec == "fp64" else "fp32"]
-    achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
+    dtype = "f64" if prec_name == "fp64" else "f32+f64"
+    peak = PEAK_TFLOPS["fp64"]
     value = L / (ms * 1e-3)
     line = {
         "metric": "leaf condensations/s + % MFMA peak; FP64 vs FP32+refine at <=1e-9 rel err",
@@ -181,6 +232,8 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": per[len(per) // 2],
+        "ms_per_step_min": per[0],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -189,48 +242,61 @@ def main() -> int:
         "config": {"workload": prob.name if len(probs) == 1 else "uneven_8_problems",
                    "leaves": L, "p": p if len(probs) == 1 else [q.p for q in probs],
                    "kappa": prob.kappa if len(probs) == 1 else [q.kappa for q in probs],
-                   "b": prob.meta.get("b"), "precision": args.prec, "parallelism": "single-gpu"},
+                   "b": prob.meta.get("b"), "precision": prec_name, "max_refine": args.max_refine,
+                   "graph_replay": use_graph, "tuned": tuned, "parallelism": "single-gpu"},
         "useful_tflops": fl["total"] * L / (ms * 1e-3) / 1e12,
         "useful_frac_fp64_peak": fl["total"] * L / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
-        "phases_ms_per_step": {k: v[0] / args.steps for k, v in phases.items() if v[1]},
         "leaves_with_nonzero_info": bad,
         "leaves_redone_fp64": redo,
-        "roofline": {"bound": "mfma", "kernel": "k_factor", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "per_launch_flop": fl["factor"] * L * args.steps / max(f_n, 1),
-                     "launch_ms": launch_ms, "launches_per_step": f_n / args.steps},
     }
-    tr = MEASURED_TRAFFIC.get((kernel_source_hash(), args.prec))
-    if tr is not None:
-        line["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
-        line["roofline"]["traffic_detail"] = dict(tr, unit="bytes per launch",
-                                                  source="rocprofv3 --pmc, calibrated")
+    if not use_graph:
+        f_ms, f_n = phases["factor"]
+        t_factor = f_ms / args.steps          # ms of factorisation launches per step
+        achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
+        line["phases_ms_per_step"] = {k: v[0] / args.steps for k, v in phases.items() if v[1]}
+        # every tile product runs on the FP64 MFMA in both precisions
+        line["roofline"] = {"bound": "mfma", "kernel": "k_factor", "achieved": achieved,
+                            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                            "traffic": None,
+                            "per_launch_flop": fl["factor"] * L * args.steps / max(f_n, 1),
+                            "launch_ms": f_ms / max(f_n, 1),
+                            "launches_per_step": f_n / args.steps}
+        tr = MEASURED_TRAFFIC.get((kernel_source_hash(), prec_name))
+        if tr is not None:
+            line["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
+            line["roofline"]["traffic_detail"] = dict(tr, unit="bytes per launch",
+                                                      source="rocprofv3 --pmc, calibrated")
 
     if not args.no_compare:
         other = hps.HPS_FP32_REFINE if prec == hps.HPS_FP64 else hps.HPS_FP64
         S2 = torch.empty_like(S)
         for _ in range(2):
-            step(other, S2)
+            condense(other, S2)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         n2 = max(3, args.steps // 2)
         e0.record()
         for _ in range(n2):
-            step(other, S2)
+            condense(other, S2)
         e1.record()
         torch.cuda.synchronize()
         ms2 = e0.elapsed_time(e1) / n2
         rel = 0.0
         for Sa, Sb in zip(B.split(S, "S"), B.split(S2, "S")):
             rel = max(rel, ((Sa - Sb).flatten(1).norm(dim=1)
-                            / Sa.flatten(1).norm(dim=1)).max().item())
+                            / Sb.flatten(1).norm(dim=1)).max().item())
         redo2 = hps.hps_batch_stats(B.batch)[1]
         line["compare"] = {"precision": "fp32+refine" if other == hps.HPS_FP32_REFINE else "fp64",
                            "leaves_redone_fp64": redo2,
                            "leaves_per_s": L / (ms2 * 1e-3), "ms_per_step": ms2,
-                           "max_refine": args.max_refine,
+                           "eager": True,
                            "max_leaf_relerr_S_vs_other": rel}
+        condense()               # leave the timed precision's X in the batch
+        torch.cuda.synchronize()
+
+    if not args.no_recover:
+        line["recover"] = recover_timing(B, max(3, args.steps // 2))
 
     if not args.no_cpu:
         print("# timing the CPU oracle", file=sys.stderr, flush=True)
