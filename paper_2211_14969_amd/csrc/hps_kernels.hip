@@ -568,69 +568,6 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
 // after step k for the forward replay, before it for the back substitution;
 // other rows contribute zero) and Y the 16 solved rows in LDS.  Each wave
 // takes a row tile and up to four right-hand-side tiles at once.
-template <typename T, int NW>
-__device__ __forceinline__ void strip_update(T *Ml, const T *Y, int YST, const int *rst,
-                                             const int *tileAny, int RT, int CT, int R, int ntj,
-                                             int k, bool after, int wv, int lane) {
-  const int nstrip = (ntj + 3) >> 2;
-  const int nall = RT * nstrip;
-  auto next_strip = [&](int t) {
-    while (t < nall && !tileAny[t / nstrip]) t += NW;
-    return t;
-  };
-  typename Mfma<T>::acc cur[4], nxt[4];
-  T acur[4], anxt[4];
-  // loads of a strip: its C tiles and its A operand (W[rows, panel k])
-  auto load_strip = [&](int t, typename Mfma<T>::acc (&dst)[4], T (&a)[4]) {
-    const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
-    const int nj = min(4, ntj - j0);
-    const T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      if (jj < nj) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dst[jj][q] = Ct[jj * 256 + q * 64 + lane];
-      }
-    }
-    const int ar = ti * 16 + (lane & 15);
-    const bool use = after ? rst[ar] > k : rst[ar] < k;
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc)
-      a[kc] = use ? -Ml[tix<T>(ar, k * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
-  };
-  int t = next_strip(wv);
-  if (t < nall) load_strip(t, cur, acur);
-  while (t < nall) {
-    const int tn = next_strip(t + NW);
-    if (tn < nall) load_strip(tn, nxt, anxt);
-    const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
-    const int nj = min(4, ntj - j0);
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      if (jj < nj) {
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-          const T b = Y[(4 * kc + (lane >> 4)) * YST + (j0 + jj) * 16 + (lane & 15)];
-          cur[jj] = Mfma<T>::op(acur[kc], b, cur[jj]);
-        }
-      }
-    }
-    T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      if (jj < nj) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = cur[jj][q];
-      }
-    }
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) cur[jj] = nxt[jj];
-#pragma unroll
-    for (int kc = 0; kc < 4; ++kc) acur[kc] = anxt[kc];
-    t = tn;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // factor2: the same factorisation for R <= 256 with panels taken in pairs.
 // Panel A's update is applied at once only to panel B's column tile; panel
@@ -1353,70 +1290,80 @@ __global__ void __launch_bounds__(64 * NW, 1) k_factor_rr(Geom g, float *M, int 
 }
 
 // ---------------------------------------------------------------------------
-// forward replay of the stored L on fresh right-hand sides (refinement)
+// Blocked triangular solves with the stored factorisation on the right-hand
+// sides held in the work matrix.  A super-step takes NB consecutive panels
+// at once: their 16-row pivot blocks are gathered into LDS, solved one after
+// another (the 16-column triangles one column per thread; each solved block
+// immediately updates the pivot blocks of the super-step that depend on it),
+// and then every remaining row of the right-hand sides receives all NB
+// updates in one MFMA pass, C -= sum_b W[r, panel b] Y_b.  The right-hand
+// sides therefore stream through memory once per NB panels instead of once
+// per panel.  Forward (refinement only): panels ascending, unit lower L11,
+// rows retired after the super-step are updated, the solved pivot rows are
+// written back into the work matrix.  Backward: panels descending, U11 with
+// its diagonal, rows retired before the super-step are updated, X (or h, or
+// u_i) written in FP64.
 // ---------------------------------------------------------------------------
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_fwdsolve(Geom g, T *M, const int *piv,
-                                                 const int *rstep, const int *skip) {
-  constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int leaf = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (skip && skip[leaf]) return;
-  const int R = g.R, RT = g.RT, CT = g.CT, NRC = CT * 16 - R, YST = NRC + 16;
-  T *Y = (T *)smem;                 // [16][YST]
-  T *Lt = Y + 16 * YST;             // [16][kPST]
-  int *rst = (int *)(Lt + 16 * kPST);
-  int *tileAny = rst + R;
-  int *pva = tileAny + RT;          // [R] all pivots of the leaf
-  T *Ml = M + leaf_stride(g) * leaf;
-  for (int r = tid; r < R; r += NT) {
-    rst[r] = rstep[(size_t)leaf * R + r];
-    pva[r] = piv[(size_t)leaf * R + r];
-  }
-  __syncthreads();
-  for (int k = 0; k < RT; ++k) {
-    const int *pv = pva + 16 * k;
-    for (int e = tid; e < 256; e += NT) {
-      const int s = e >> 4, q = e & 15;
-      Lt[s * kPST + q] = Ml[tix<T>(pv[s], k * 16 + q, CT)];
-    }
-    for (int t = tid; t < RT; t += NT) {
-      int a = 0;
-      for (int q = 0; q < 16; ++q) a |= (rst[t * 16 + q] > k);
-      tileAny[t] = a;
-    }
-    __syncthreads();
-    for (int jr = tid; jr < NRC; jr += NT) {
-      T u[16];
+constexpr int kSolveNB = 4;   // panels per super-step
+
+// C -= sum over the nbk blocks of W[r, panel pb[i]] * Yb[i] on the row tiles
+// flagged in tileAny, for rows retired after kmax (after) or before kmin.
+template <typename T, int NW>
+__device__ __forceinline__ void strip_update_nb(T *Ml, const T *Y, int YST, const int *rst,
+                                                const int *tileAny, int RT, int CT, int R,
+                                                int ntj, int k0, int nbk, int dir, bool after,
+                                                int kbound, int wv, int lane) {
+  const int nstrip = (ntj + 3) >> 2;
+  const int nall = RT * nstrip;
+  for (int t = wv; t < nall; t += NW) {
+    const int ti = t / nstrip;
+    if (!tileAny[ti]) continue;
+    const int j0 = (t - ti * nstrip) * 4;
+    const int nj = min(4, ntj - j0);
+    T *Ct = Ml + ((size_t)(ti * CT + (R >> 4) + j0) << 8);
+    const int ar = ti * 16 + (lane & 15);
+    const bool use = after ? rst[ar] > kbound : rst[ar] < kbound;
+    typename Mfma<T>::acc c[4];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) u[s] = Ml[tix<T>(pv[s], R + jr, CT)];
+    for (int jj = 0; jj < 4; ++jj) {
+      if (jj < nj) {
 #pragma unroll
-      for (int s = 1; s < 16; ++s) {
-        T acc = u[s];
-#pragma unroll
-        for (int q = 0; q < s; ++q) acc -= Lt[s * kPST + q] * u[q];
-        u[s] = acc;
-      }
-#pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        Y[s * YST + jr] = u[s];
-        Ml[tix<T>(pv[s], R + jr, CT)] = u[s];
+        for (int q = 0; q < 4; ++q) c[jj][q] = Ct[jj * 256 + q * 64 + lane];
       }
     }
-    __syncthreads();
-    strip_update<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k, /*after=*/true, wv,
-                        lane);
-    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < nbk; ++i) {
+      const int pb = k0 + dir * i;
+      T a[4];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        a[kc] = use ? -Ml[tix<T>(ar, pb * 16 + 4 * kc + (lane >> 4), CT)] : T(0);
+      const T *Yb = Y + (size_t)i * 16 * YST;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const T bq = Yb[(4 * kc + (lane >> 4)) * YST + (j0 + jj) * 16 + (lane & 15)];
+            c[jj] = Mfma<T>::op(a[kc], bq, c[jj]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      if (jj < nj) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = (T)c[jj][q];
+      }
+    }
   }
 }
 
-// ---------------------------------------------------------------------------
-// back substitution U X = Y over the right-hand-side columns
-// ---------------------------------------------------------------------------
-template <typename T, int NT>
-__global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
-                                                  const int *rstep, BackOut o, Sel sel) {
-  constexpr int NW = NT / 64;
+template <typename T, int NT, bool FWD>
+__global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, const int *rstep,
+                                                 BackOut o, Sel sel) {
+  constexpr int NW = NT / 64, NB = kSolveNB;
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int leaf;
@@ -1425,10 +1372,11 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb;
   const int NRC = CT * 16 - R, YST = NRC + 16;
   double *red = (double *)smem;     // [NW]
-  T *Y = (T *)(red + NW);           // [16][YST]
-  T *Ut = Y + 16 * YST;             // [16][kPST]
-  T *Ud = Ut + 16 * kPST;           // [16] reciprocals of the diagonal of U11
-  int *rst = (int *)(Ud + 16);
+  T *Y = (T *)(red + NW);           // [NB][16][YST] pivot blocks of the super-step
+  T *Tt = Y + NB * 16 * YST;        // [16][kPST] triangle of the current panel
+  T *Td = Tt + 16 * kPST;           // [16] reciprocals of its diagonal (backward)
+  T *Tx = Td + 16;                  // [NB][16][kPST] couplings to the later blocks
+  int *rst = (int *)(Tx + NB * 16 * kPST);
   int *tileAny = rst + R;
   int *pva = tileAny + RT;          // [R] all pivots of the leaf
   T *Ml = M + leaf_stride(g) * wi;
@@ -1438,64 +1386,102 @@ __global__ void __launch_bounds__(NT) k_backsolve(Geom g, T *M, const int *piv,
     pva[r] = piv[(size_t)wi * R + r];
   }
   __syncthreads();
-  for (int k = RT - 1; k >= 0; --k) {
-    const int *pv = pva + 16 * k;
-    for (int e = tid; e < 256; e += NT) {
-      const int s = e >> 4, q = e & 15;
-      const T u = Ml[tix<T>(pv[s], k * 16 + q, CT)];
-      Ut[s * kPST + q] = u;
-      if (q == s) Ud[s] = T(1) / u;
-    }
-    for (int e = tid; e < 16 * NRC; e += NT) {
-      const int s = e / NRC, jr = e - s * NRC;
-      Y[s * YST + jr] = Ml[tix<T>(pv[s], R + jr, CT)];
+  const int dir = FWD ? 1 : -1;
+  for (int k0 = FWD ? 0 : RT - 1; FWD ? k0 < RT : k0 >= 0; k0 += dir * NB) {
+    const int nbk = FWD ? min(NB, RT - k0) : min(NB, k0 + 1);
+    const int klast = k0 + dir * (nbk - 1);
+    // gather the pivot blocks of the super-step; flag the row tiles that the
+    // closing update touches
+    for (int e = tid; e < nbk * 16 * NRC; e += NT) {
+      const int i = e / (16 * NRC), rem = e - i * 16 * NRC, s = rem / NRC, jr = rem - s * NRC;
+      Y[(i * 16 + s) * YST + jr] = Ml[tix<T>(pva[16 * (k0 + dir * i) + s], R + jr, CT)];
     }
     for (int t = tid; t < RT; t += NT) {
       int a = 0;
-      for (int q = 0; q < 16; ++q) a |= (rst[t * 16 + q] < k);
+      for (int q = 0; q < 16; ++q) {
+        const int st = rst[t * 16 + q];
+        a |= FWD ? (st > klast) : (st < klast);
+      }
       tileAny[t] = a;
     }
-    __syncthreads();
-    for (int jr = tid; jr < NRC; jr += NT) {
-      T x[16];
-#pragma unroll
-      for (int s = 15; s >= 0; --s) {
-        T acc = Y[s * YST + jr];
-#pragma unroll
-        for (int q = s + 1; q < 16; ++q) acc -= Ut[s * kPST + q] * x[q];
-        x[s] = acc * Ud[s];
+    for (int i = 0; i < nbk; ++i) {
+      const int b = k0 + dir * i;
+      const int *pv = pva + 16 * b;
+      // triangle of panel b, and the couplings of the later pivot blocks
+      // to panel b's unknowns
+      for (int e = tid; e < 256; e += NT) {
+        const int s = e >> 4, q = e & 15;
+        const T u = Ml[tix<T>(pv[s], b * 16 + q, CT)];
+        Tt[s * kPST + q] = u;
+        if (!FWD && q == s) Td[s] = T(1) / u;
       }
+      for (int e = tid; e < (nbk - 1 - i) * 256; e += NT) {
+        const int i2 = i + 1 + (e >> 8), s2 = (e >> 4) & 15, q = e & 15;
+        Tx[(i2 * 16 + s2) * kPST + q] = Ml[tix<T>(pva[16 * (k0 + dir * i2) + s2], b * 16 + q, CT)];
+      }
+      __syncthreads();
+      for (int jr = tid; jr < NRC; jr += NT) {
+        T x[16];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) Y[s * YST + jr] = x[s];
-      if (jr < g.nrhs) {
+        for (int s = 0; s < 16; ++s) x[s] = Y[(i * 16 + s) * YST + jr];
+        if (FWD) {
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-          const int i = k * 16 + s;
-          if (i >= ni) continue;
-          const double v = (double)x[s];
-          if (o.mode == BACK_UI) {
-            o.ui[(size_t)leaf * ni + i] = v;
-          } else {
-            double *dst = (jr < nb) ? o.Xt + ((size_t)leaf * nb + jr) * ni + i
-                                    : o.h + (size_t)leaf * ni + i;
-            if (o.mode == BACK_STORE) {
-              *dst = v;
+          for (int s = 0; s < 16; ++s) {
+#pragma unroll
+            for (int q = s + 1; q < 16; ++q) x[q] -= Tt[q * kPST + s] * x[s];
+          }
+        } else {
+#pragma unroll
+          for (int s = 15; s >= 0; --s) {
+            x[s] *= Td[s];
+#pragma unroll
+            for (int q = 0; q < s; ++q) x[q] -= Tt[q * kPST + s] * x[s];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s) Y[(i * 16 + s) * YST + jr] = x[s];
+        // the later pivot blocks of the super-step take panel b's update
+#pragma unroll 1
+        for (int i2 = i + 1; i2 < nbk; ++i2) {
+#pragma unroll
+          for (int s2 = 0; s2 < 16; ++s2) {
+            T acc = Y[(i2 * 16 + s2) * YST + jr];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc -= Tx[(i2 * 16 + s2) * kPST + q] * x[q];
+            Y[(i2 * 16 + s2) * YST + jr] = acc;
+          }
+        }
+        if (FWD) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) Ml[tix<T>(pv[s], R + jr, CT)] = x[s];
+        } else if (jr < g.nrhs) {
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            const int ii = b * 16 + s;
+            if (ii >= ni) continue;
+            const double v = (double)x[s];
+            if (o.mode == BACK_UI) {
+              o.ui[(size_t)leaf * ni + ii] = v;
             } else {
-              *dst += v;
-              nd += v * v;
+              double *dst = (jr < nb) ? o.Xt + ((size_t)leaf * nb + jr) * ni + ii
+                                      : o.h + (size_t)leaf * ni + ii;
+              if (o.mode == BACK_STORE) {
+                *dst = v;
+              } else {
+                *dst += v;
+                nd += v * v;
+              }
             }
           }
         }
       }
-    }
-    __syncthreads();
-    if (k > 0) {
-      strip_update<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k, /*after=*/false, wv,
-                          lane);
       __syncthreads();
     }
+    strip_update_nb<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k0, nbk, dir, FWD,
+                           klast, wv, lane);
+    __syncthreads();
   }
-  if (o.mode == BACK_ACCUM) {
+  if (!FWD && o.mode == BACK_ACCUM) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
     if (lane == 0) red[wv] = nd;
@@ -1863,7 +1849,8 @@ template <typename T>
 size_t solve_lds(const Geom &g) {
   const int NRC = g.CT * 16 - g.R;
   size_t b = sizeof(double) * (kSolveNT / 64);
-  b += sizeof(T) * (16 * (size_t)(NRC + 16) + 16 * kPST + 16);
+  b += sizeof(T) * ((size_t)kSolveNB * 16 * (NRC + 16) + 16 * kPST + 16 +
+                    (size_t)kSolveNB * 16 * kPST);
   b += sizeof(int) * (2 * (size_t)g.R + g.RT);
   return b;
 }
@@ -2051,40 +2038,34 @@ hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *X
   return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
 }
 
+template <typename T, bool FWD>
+hipError_t launch_trisolve(const Geom &g, int nleaf, T *M, const int *piv, const int *rstep,
+                           const BackOut &o, hipStream_t s, const Sel &sel) {
+  const size_t lds = solve_lds<T>(g);
+  hipError_t e = set_lds(k_trisolve<T, kSolveNT, FWD>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_trisolve<T, kSolveNT, FWD>), dim3(nleaf), dim3(kSolveNT), lds, s, g, M,
+                     piv, rstep, o, sel);
+  return hipGetLastError();
+}
+
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
-  if (fp32) {
-    const size_t lds = solve_lds<float>(g);
-    hipError_t e = set_lds(k_backsolve<float, kSolveNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backsolve<float, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (float *)M, piv, rstep, o, sel);
-  } else {
-    const size_t lds = solve_lds<double>(g);
-    hipError_t e = set_lds(k_backsolve<double, kSolveNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_backsolve<double, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (double *)M, piv, rstep, o, sel);
-  }
-  return hipGetLastError();
+  if (fp32) return launch_trisolve<float, false>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
+  return launch_trisolve<double, false>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
 }
 
 hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                            const int *rstep, const int *skip, hipStream_t s) {
-  if (fp32) {
-    const size_t lds = solve_lds<float>(g);
-    hipError_t e = set_lds(k_fwdsolve<float, kSolveNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fwdsolve<float, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (float *)M, piv, rstep, skip);
-  } else {
-    const size_t lds = solve_lds<double>(g);
-    hipError_t e = set_lds(k_fwdsolve<double, kSolveNT>, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fwdsolve<double, kSolveNT>), dim3(nleaf), dim3(kSolveNT), lds, s, g,
-                       (double *)M, piv, rstep, skip);
-  }
-  return hipGetLastError();
+  BackOut o;
+  o.Xt = nullptr;
+  o.h = nullptr;
+  o.ui = nullptr;
+  o.norms = nullptr;
+  o.skip = skip;
+  o.mode = BACK_STORE;
+  if (fp32) return launch_trisolve<float, true>(g, nleaf, (float *)M, piv, rstep, o, s, Sel());
+  return launch_trisolve<double, true>(g, nleaf, (double *)M, piv, rstep, o, s, Sel());
 }
 
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
