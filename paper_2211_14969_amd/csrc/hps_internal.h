@@ -70,9 +70,6 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
                             const int *piv, const int *rstep, const BackOut &o,
                             hipStream_t s, const Sel &sel = Sel());
-hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M,
-                           const int *piv, const int *rstep, const int *skip,
-                           hipStream_t s);
 // forward + back substitution of FP32 factors on the right-hand sides held in
 // the work matrix (the refinement residual), accumulating into o.Xt / o.h
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,

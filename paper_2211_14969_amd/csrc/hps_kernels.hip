@@ -1360,7 +1360,9 @@ __device__ __forceinline__ void strip_update_nb(T *Ml, const T *Y, int YST, cons
   }
 }
 
-template <typename T, int NT, bool FWD>
+// PASSES: 1 backward only, 2 forward only, 3 forward then backward (the
+// refinement correction in one launch).
+template <typename T, int NT, int PASSES>
 __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, const int *rstep,
                                                  BackOut o, Sel sel) {
   constexpr int NW = NT / 64, NB = kSolveNB;
@@ -1386,6 +1388,9 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
     pva[r] = piv[(size_t)wi * R + r];
   }
   __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+  const bool FWD = pass == 0;
+  if (!(PASSES & (FWD ? 2 : 1))) continue;
   const int dir = FWD ? 1 : -1;
   for (int k0 = FWD ? 0 : RT - 1; FWD ? k0 < RT : k0 >= 0; k0 += dir * NB) {
     const int nbk = FWD ? min(NB, RT - k0) : min(NB, k0 + 1);
@@ -1481,7 +1486,8 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
                            klast, wv, lane);
     __syncthreads();
   }
-  if (!FWD && o.mode == BACK_ACCUM) {
+  }
+  if ((PASSES & 1) && o.mode == BACK_ACCUM) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
     if (lane == 0) red[wv] = nd;
@@ -2038,42 +2044,26 @@ hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *X
   return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
 }
 
-template <typename T, bool FWD>
+template <typename T, int PASSES>
 hipError_t launch_trisolve(const Geom &g, int nleaf, T *M, const int *piv, const int *rstep,
                            const BackOut &o, hipStream_t s, const Sel &sel) {
   const size_t lds = solve_lds<T>(g);
-  hipError_t e = set_lds(k_trisolve<T, kSolveNT, FWD>, lds);
+  hipError_t e = set_lds(k_trisolve<T, kSolveNT, PASSES>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_trisolve<T, kSolveNT, FWD>), dim3(nleaf), dim3(kSolveNT), lds, s, g, M,
+  hipLaunchKernelGGL((k_trisolve<T, kSolveNT, PASSES>), dim3(nleaf), dim3(kSolveNT), lds, s, g, M,
                      piv, rstep, o, sel);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
-  if (fp32) return launch_trisolve<float, false>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
-  return launch_trisolve<double, false>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
-}
-
-hipError_t launch_fwdsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
-                           const int *rstep, const int *skip, hipStream_t s) {
-  BackOut o;
-  o.Xt = nullptr;
-  o.h = nullptr;
-  o.ui = nullptr;
-  o.norms = nullptr;
-  o.skip = skip;
-  o.mode = BACK_STORE;
-  if (fp32) return launch_trisolve<float, true>(g, nleaf, (float *)M, piv, rstep, o, s, Sel());
-  return launch_trisolve<double, true>(g, nleaf, (double *)M, piv, rstep, o, s, Sel());
+  if (fp32) return launch_trisolve<float, 1>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
+  return launch_trisolve<double, 1>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
 }
 
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
                                const int *rstep, const BackOut &o, hipStream_t s) {
-
-  const hipError_t e = launch_fwdsolve(g, nleaf, true, M, piv, rstep, o.skip, s);
-  if (e != hipSuccess) return e;
-  return launch_backsolve(g, nleaf, true, M, piv, rstep, o, s);
+  return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel());
 }
 
 hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info, int it,
