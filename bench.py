@@ -118,7 +118,7 @@ def main() -> int:
     ap.add_argument("--prec", choices=("fp64", "fp32"), default=None,
                     help="precision of the timed path (fp32 = FP32 + FP64 refinement); "
                          "default fp64, fp32 for the uneven batch")
-    ap.add_argument("--max-refine", type=int, default=2)
+    ap.add_argument("--max-refine", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",

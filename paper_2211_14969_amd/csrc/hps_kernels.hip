@@ -1657,15 +1657,14 @@ __global__ void k_collect(int nleaf, int *info, int *list, int *count, int *tota
 // ---------------------------------------------------------------------------
 // Schur complement S = A_bb - A_bi X and w = A_bi h in FP64.  A_bi has p-2
 // nonzeros per row (the normal derivative along one grid line) and A_bb two.
-// Columns of X are staged through LDS a few at a time so that every global
-// read is coalesced.
+// Columns of X are staged through LDS sixteen (large ni: eight) at a time,
+// the LDS sized by ni, so that every global read is coalesced.
 // ---------------------------------------------------------------------------
-constexpr int kSchurCols = 8;
-
 __global__ void __launch_bounds__(256) k_schur(Geom g, const double *Xt, const double *h,
-                                               double *S, double *w, int *info) {
+                                               double *S, double *w, int *info, int kSchurCols) {
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sD0[32], sD1[32];   // rows 0 and p-1 of D
-  __shared__ double xs[kSchurCols * 900];
+  double *xs = (double *)smem;          // [kSchurCols][ni] staged columns of [X h]
   __shared__ int bad;
   const int leaf = blockIdx.x;
   const int p = g.p, m = g.m, ni = g.ni, nb = g.nb;
@@ -2082,7 +2081,12 @@ hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *tota
 
 hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h, double *S,
                         double *w, int *info, hipStream_t s) {
-  hipLaunchKernelGGL(k_schur, dim3(nleaf), dim3(256), 0, s, g, Xt, h, S, w, info);
+  // sixteen columns per pass while that keeps LDS under 32 KB, else eight
+  const int cols = g.ni * 16 * sizeof(double) <= 32 * 1024 ? 16 : 8;
+  const size_t lds = sizeof(double) * cols * (size_t)g.ni;
+  hipError_t e = set_lds(k_schur, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_schur, dim3(nleaf), dim3(256), lds, s, g, Xt, h, S, w, info, cols);
   return hipGetLastError();
 }
 
