@@ -74,6 +74,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build it with `python -m paper_2211_14969_amd.build`")
+    # torch first: its HIP runtime must be the one the library binds to, or the
+    # process would hold two runtimes whose streams and devices do not mix
+    _torch()
     L = ctypes.CDLL(path)
     vp, ip, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double
     L.hps_status_string.restype = ctypes.c_char_p
