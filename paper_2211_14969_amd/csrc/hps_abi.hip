@@ -456,18 +456,22 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
         o.mode = hps::BACK_ACCUM;
         o.skip = conv;
         o.norms = nrm;
+        int nsol = 1;   // column chunks of the previous correction solve
         for (int it = 0; it <= nref; ++it) {
           if (it == nref && it > 0 && tl >= 1.0) break;  // no final test wanted
+          const int nch = hps::refine_chunks(g, it);
           HPS_TRY(timed(b->ctx, 6, [&] {
-            return hps::launch_residual(g, n, (float *)b->ws, Xt, hh, fc, conv, nrm, s);
+            return hps::launch_residual(g, n, (float *)b->ws, Xt, hh, fc, conv, nrm, nch, s);
           }));
           HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_convcheck(n, nrm, tl, conv, inf, it, it == nref ? 1 : 0, s);
+            return hps::launch_convcheck(n, nrm, tl, conv, inf, it, it == nref ? 1 : 0, nch, nsol,
+                                         s);
           }));
           if (it == nref) break;
           HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_refine_solve(g, n, b->ws, b->piv, b->rstep, o, s);
+            return hps::launch_refine_solve(g, n, b->ws, b->piv, b->rstep, o, nch, s);
           }));
+          nsol = nch;
         }
         // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
         // for an FP32 factorisation, e.g. near a leaf resonance) are condensed

@@ -51,15 +51,18 @@ struct BackOut {
   double *Xt;        // [nleaf][nb][ni]
   double *h;         // [nleaf][ni]   (nullptr when no f column)
   double *ui;        // [nleaf][ni]   (BACK_UI)
-  double *norms;     // [nleaf][kNormStride]: slot 5 receives ||dX||^2 (BACK_ACCUM)
+  double *norms;     // [nleaf][kNormStride]: slot 16 + chunk receives ||dX||^2 (BACK_ACCUM)
   const int *skip;   // [nleaf] leaves to leave untouched (nullptr = none)
   int mode;
 };
 
 constexpr int kInfoActive = 0x7fffffff;
 // refinement norms per leaf: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2,
-// 5 ||dX||^2 of the last correction, 6 relative size of the first correction
-constexpr int kNormStride = 8;
+// 5 ||dX||^2 of the last correction, 6 relative size of the first correction;
+// per column chunk c < kMaxChunks: 8+c ||r||^2, 12+c ||X||^2 (residual) and
+// 16+c ||dX||^2 (correction), summed in chunk order by the stop test
+constexpr int kMaxChunks = 4;
+constexpr int kNormStride = 24;
 
 // Launchers (hps_kernels.hip).  All enqueue on `s` and return hipError_t.
 // Factorisation of the work matrices; step 0 forms them from the operator
@@ -73,12 +76,16 @@ hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M,
 // forward + back substitution of FP32 factors on the right-hand sides held in
 // the work matrix (the refinement residual), accumulating into o.Xt / o.h
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
-                               const int *rstep, const BackOut &o, hipStream_t s);
+                               const int *rstep, const BackOut &o, int nch, hipStream_t s);
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip,
-                           double *norms, hipStream_t s);
+                           double *norms, int nch, hipStream_t s);
 hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
-                            int it, int last, hipStream_t s);
+                            int it, int last, int nres, int nsol, hipStream_t s);
+// column chunks (workgroups per leaf) of the refinement residual and
+// correction solve; more than one only for iterations after the first,
+// where the few leaves left would otherwise leave the GPU idle
+int refine_chunks(const Geom &g, int it);
 hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total,
                           hipStream_t s);
 hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h,

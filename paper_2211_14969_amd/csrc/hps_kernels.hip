@@ -1364,7 +1364,7 @@ __device__ __forceinline__ void strip_update_nb(T *Ml, const T *Y, int YST, cons
 // refinement correction in one launch).
 template <typename T, int NT, int PASSES>
 __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, const int *rstep,
-                                                 BackOut o, Sel sel) {
+                                                 BackOut o, Sel sel, int CW) {
   constexpr int NW = NT / 64, NB = kSolveNB;
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1372,7 +1372,9 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
   if (!resolve_leaf(sel, leaf)) return;
   if (o.skip && o.skip[leaf]) return;
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb;
-  const int NRC = CT * 16 - R, YST = NRC + 16;
+  // this workgroup's right-hand-side columns: [c0, c0 + NRC) of the CW-wide
+  // chunk blockIdx.y (whole 16-column tiles)
+  const int c0 = blockIdx.y * CW, NRC = min(CW, CT * 16 - R - c0), YST = CW + 16;
   double *red = (double *)smem;     // [NW]
   T *Y = (T *)(red + NW);           // [NB][16][YST] pivot blocks of the super-step
   T *Tt = Y + NB * 16 * YST;        // [16][kPST] triangle of the current panel
@@ -1399,7 +1401,7 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
     // closing update touches
     for (int e = tid; e < nbk * 16 * NRC; e += NT) {
       const int i = e / (16 * NRC), rem = e - i * 16 * NRC, s = rem / NRC, jr = rem - s * NRC;
-      Y[(i * 16 + s) * YST + jr] = Ml[tix<T>(pva[16 * (k0 + dir * i) + s], R + jr, CT)];
+      Y[(i * 16 + s) * YST + jr] = Ml[tix<T>(pva[16 * (k0 + dir * i) + s], R + c0 + jr, CT)];
     }
     for (int t = tid; t < RT; t += NT) {
       int a = 0;
@@ -1458,8 +1460,8 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
         }
         if (FWD) {
 #pragma unroll
-          for (int s = 0; s < 16; ++s) Ml[tix<T>(pv[s], R + jr, CT)] = x[s];
-        } else if (jr < g.nrhs) {
+          for (int s = 0; s < 16; ++s) Ml[tix<T>(pv[s], R + c0 + jr, CT)] = x[s];
+        } else if (c0 + jr < g.nrhs) {
 #pragma unroll
           for (int s = 0; s < 16; ++s) {
             const int ii = b * 16 + s;
@@ -1468,8 +1470,9 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
             if (o.mode == BACK_UI) {
               o.ui[(size_t)leaf * ni + ii] = v;
             } else {
-              double *dst = (jr < nb) ? o.Xt + ((size_t)leaf * nb + jr) * ni + ii
-                                      : o.h + (size_t)leaf * ni + ii;
+              const int col = c0 + jr;
+              double *dst = (col < nb) ? o.Xt + ((size_t)leaf * nb + col) * ni + ii
+                                       : o.h + (size_t)leaf * ni + ii;
               if (o.mode == BACK_STORE) {
                 *dst = v;
               } else {
@@ -1482,8 +1485,8 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
       }
       __syncthreads();
     }
-    strip_update_nb<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R, NRC >> 4, k0, nbk, dir, FWD,
-                           klast, wv, lane);
+    strip_update_nb<T, NW>(Ml, Y, YST, rst, tileAny, RT, CT, R + c0, NRC >> 4, k0, nbk, dir,
+                           FWD, klast, wv, lane);
     __syncthreads();
   }
   }
@@ -1495,7 +1498,7 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
     if (tid == 0) {
       double a = 0.0;
       for (int w = 0; w < NW; ++w) a += red[w];
-      o.norms[kNormStride * (size_t)leaf + 5] = a;
+      o.norms[kNormStride * (size_t)leaf + 16 + blockIdx.y] = a;
     }
   }
 }
@@ -1507,10 +1510,11 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
 // per leaf; a thread owns one row and keeps its coefficients in
 // registers; CW columns of [X h] at a time are staged in LDS (coalesced
 // reads of Xt); each line weight is formed once per row and chunk and used
-// for all CW columns.  The residual is written in FP32 into the
-// right-hand-side columns of the work matrix for the correction solve (zero
-// in the padding rows), and the squared Frobenius norms of r and X are
-// stored per leaf for the stop test.
+// for all CW columns.  A leaf's columns may be split over gridDim.y
+// workgroups.  The residual is written in FP32 into the right-hand-side
+// columns of the work matrix for the correction solve (zero in the padding
+// rows), and the squared Frobenius norms of r and X are stored per leaf and
+// column chunk for the stop test.
 // ---------------------------------------------------------------------------
 template <int NT, int CW>
 __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const double *Xt,
@@ -1543,7 +1547,11 @@ __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const doubl
     kb = g.k2b ? g.k2b[n] : 0.0;
   }
   double nr = 0.0, nx = 0.0;
-  for (int c0 = 0; c0 < ncol; c0 += CW) {
+  // this workgroup's columns: chunk blockIdx.y of gridDim.y, whole CW groups
+  const int ngrp = (ncol + CW - 1) / CW;
+  const int g0 = (ngrp * (int)blockIdx.y) / (int)gridDim.y;
+  const int g1 = (ngrp * ((int)blockIdx.y + 1)) / (int)gridDim.y;
+  for (int c0 = g0 * CW; c0 < min(g1 * CW, ncol); c0 += CW) {
     const int cw = min(CW, ncol - c0);
     __syncthreads();
     for (int e = threadIdx.x; e < cw * ni; e += NT) {
@@ -1606,7 +1614,7 @@ __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const doubl
   if (threadIdx.x < 2) {
     double a = 0.0;
     for (int w = 0; w < NT / 64; ++w) a += red[w][threadIdx.x];
-    norms[kNormStride * (size_t)leaf + threadIdx.x] = a;
+    norms[kNormStride * (size_t)leaf + 8 + 4 * threadIdx.x + blockIdx.y] = a;
   }
 }
 
@@ -1622,14 +1630,24 @@ __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const doubl
 // cond(A_ii) 2^-53, lies above tol) never passes.  An exactly zero residual
 // passes; tol >= 1 passes on the final check without a test.  On the final
 // check a leaf that did not pass is flagged -1.
-// norms[kNormStride l + ...]: 0 ||r||^2, 1 ||X||^2, 4 previous ||r||^2,
-// 5 ||dX||^2 of the last correction, 6 the relative size of the first
+// norms[kNormStride l + ...]: 0 ||r||^2, 1 ||X||^2 (sums of the nres
+// residual chunks' partial sums), 4 previous ||r||^2, 5 ||dX||^2 of the last
+// correction (sum of its nsol chunks), 6 the relative size of the first
 // correction.
 __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
-                            int it, int last) {
+                            int it, int last, int nres, int nsol) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaf || conv[l]) return;
   double *n = norms + kNormStride * (size_t)l;
+  n[0] = n[1] = 0.0;
+  for (int c = 0; c < nres; ++c) {
+    n[0] += n[8 + c];
+    n[1] += n[12 + c];
+  }
+  if (it > 0) {
+    n[5] = 0.0;
+    for (int c = 0; c < nsol; ++c) n[5] += n[16 + c];
+  }
   bool ok = n[0] == 0.0 || (tol >= 1.0 && last);
   if (it == 1) n[6] = n[1] > 0.0 ? sqrt(n[5] / n[1]) : 1.0;
   if (!ok && tol < 1.0 && it > 0 && n[4] > 0.0) {
@@ -1851,10 +1869,9 @@ int pick_ch(const Geom &g) {
 
 
 template <typename T>
-size_t solve_lds(const Geom &g) {
-  const int NRC = g.CT * 16 - g.R;
+size_t solve_lds(const Geom &g, int CW) {
   size_t b = sizeof(double) * (kSolveNT / 64);
-  b += sizeof(T) * ((size_t)kSolveNB * 16 * (NRC + 16) + 16 * kPST + 16 +
+  b += sizeof(T) * ((size_t)kSolveNB * 16 * (CW + 16) + 16 * kPST + 16 +
                     (size_t)kSolveNB * 16 * kPST);
   b += sizeof(int) * (2 * (size_t)g.R + g.RT);
   return b;
@@ -2026,31 +2043,35 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
 template <int NT, int CW>
 hipError_t launch_residual_t(const Geom &g, int nleaf, float *M32, const double *Xt,
                              const double *h, const double *f, const int *skip, double *norms,
-                             hipStream_t s) {
-  if (g.R > NT) return hipErrorInvalidValue;
+                             int nch, hipStream_t s) {
+  if (g.R > NT || nch < 1 || nch > kMaxChunks) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * (2 * (size_t)g.p * g.p + (size_t)CW * g.ni);
   hipError_t e = set_lds(k_residual<NT, CW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_residual<NT, CW>), dim3(nleaf), dim3(NT), lds, s, g, M32, Xt, h, f, skip,
-                     norms);
+  hipLaunchKernelGGL((k_residual<NT, CW>), dim3(nleaf, nch), dim3(NT), lds, s, g, M32, Xt, h, f,
+                     skip, norms);
   return hipGetLastError();
 }
 
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip, double *norms,
-                           hipStream_t s) {
-  if (g.R <= 256) return launch_residual_t<256, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
-  return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, s);
+                           int nch, hipStream_t s) {
+  if (g.R <= 256) return launch_residual_t<256, 8>(g, nleaf, M32, Xt, h, f, skip, norms, nch, s);
+  return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, nch, s);
 }
 
 template <typename T, int PASSES>
 hipError_t launch_trisolve(const Geom &g, int nleaf, T *M, const int *piv, const int *rstep,
-                           const BackOut &o, hipStream_t s, const Sel &sel) {
-  const size_t lds = solve_lds<T>(g);
+                           const BackOut &o, hipStream_t s, const Sel &sel, int nch = 1) {
+  const int NRC = g.CT * 16 - g.R;
+  const int cw = ((NRC / 16 + nch - 1) / nch) * 16;   // whole tiles per chunk
+  const int nck = (NRC + cw - 1) / cw;
+  if (nck != nch || nck > kMaxChunks) return hipErrorInvalidValue;
+  const size_t lds = solve_lds<T>(g, cw);
   hipError_t e = set_lds(k_trisolve<T, kSolveNT, PASSES>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_trisolve<T, kSolveNT, PASSES>), dim3(nleaf), dim3(kSolveNT), lds, s, g, M,
-                     piv, rstep, o, sel);
+  hipLaunchKernelGGL((k_trisolve<T, kSolveNT, PASSES>), dim3(nleaf, nck), dim3(kSolveNT), lds, s,
+                     g, M, piv, rstep, o, sel, cw);
   return hipGetLastError();
 }
 
@@ -2061,14 +2082,25 @@ hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const 
 }
 
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
-                               const int *rstep, const BackOut &o, hipStream_t s) {
-  return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel());
+                               const int *rstep, const BackOut &o, int nch, hipStream_t s) {
+  return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel(), nch);
+}
+
+// The first refinement iteration covers every leaf in one workgroup each;
+// later ones are left with the few leaves still refining, so their columns
+// are split over up to four workgroups (the chunk count of the solve is the
+// number of 16-column tiles it can split into, at most four).
+int refine_chunks(const Geom &g, int it) {
+  if (it == 0) return 1;
+  const int tiles = (g.CT * 16 - g.R) / 16;
+  const int per = (tiles + kMaxChunks - 1) / kMaxChunks;   // tiles per chunk
+  return (tiles + per - 1) / per;
 }
 
 hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int *info, int it,
-                            int last, hipStream_t s) {
+                            int last, int nres, int nsol, hipStream_t s) {
   hipLaunchKernelGGL(k_convcheck, dim3((nleaf + 255) / 256), dim3(256), 0, s, nleaf, norms, tol,
-                     conv, info, it, last);
+                     conv, info, it, last, nres, nsol);
   return hipGetLastError();
 }
 
