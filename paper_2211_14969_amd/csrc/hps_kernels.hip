@@ -2086,12 +2086,14 @@ hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv
   return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel(), nch);
 }
 
-// The first refinement iteration covers every leaf in one workgroup each;
-// later ones are left with the few leaves still refining, so their columns
-// are split over up to four workgroups (the chunk count of the solve is the
-// number of 16-column tiles it can split into, at most four).
+// The first two refinement iterations cover every leaf, or about half of
+// them on the hardest workloads, in one workgroup each (splitting would only
+// re-read the factors); later ones are left with the few leaves still
+// refining, so their columns are split over up to four workgroups (the
+// chunk count is the number of 16-column tiles the solve splits into, at
+// most four).
 int refine_chunks(const Geom &g, int it) {
-  if (it == 0) return 1;
+  if (it <= 1) return 1;
   const int tiles = (g.CT * 16 - g.R) / 16;
   const int per = (tiles + kMaxChunks - 1) / kMaxChunks;   // tiles per chunk
   return (tiles + per - 1) / per;
