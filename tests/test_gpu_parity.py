@@ -361,3 +361,24 @@ def test_invalid_arguments_enqueue_nothing(torch):
         with pytest.raises(hps.HpsError):
             hps.hps_leaf_build(B.ctx, [bad])
     B.close()
+
+
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+def test_workspace_chunking_matches_single_pass(torch, prec, monkeypatch):
+    """A workspace cap smaller than the batch condenses the leaves in several
+    passes; every leaf's results are the same as in one pass (the leaves are
+    independent), and recovery from the stored X agrees too."""
+    probs = [_small(16, 4), _small(12, 3)]
+    _say(f"workspace chunking prec={prec}")
+    B1 = _batch(probs)
+    S1, w1, i1, _ = B1.condense(prec=prec, max_refine=3, sync=True)
+    ub = torch.randn(B1.nb_total, dtype=torch.float64, device="cuda")
+    u1 = B1.recover(ub, sync=True)
+    monkeypatch.setenv("HPS_WORKSPACE_MB", "1")     # about two p = 16 leaves per pass
+    B2 = _batch(probs)
+    S2, w2, i2, _ = B2.condense(prec=prec, max_refine=3, sync=True)
+    u2 = B2.recover(ub, sync=True)
+    assert torch.equal(S1, S2) and torch.equal(i1, i2)
+    assert torch.equal(u1, u2)
+    B1.close()
+    B2.close()
