@@ -336,6 +336,59 @@ __device__ __forceinline__ T abs_key(T v) {
   return (a != a) ? T(INFINITY) : a;  // NaN is picked first, then propagates
 }
 
+// Workgroup-wide elimination of one 16-column panel held in LDS (R > 256):
+// per column, every thread scans its rows, a wavefront reduction and an LDS
+// reduction over the wavefronts find the pivot (largest magnitude among the
+// active rows, ties to the lowest row), and every thread updates its rows.
+template <typename T, int NT>
+__device__ __forceinline__ void panel_wg(T *P, int R, int k, int *pv, int *rst, int *zeroPiv,
+                                         T *redv, int *redi) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int c = 0; c < 16; ++c) {
+    T best = T(-1);
+    int bi = INT_MAX;
+    for (int r = tid; r < R; r += NT) {
+      if (rst[r] != kInfoActive) continue;
+      const T v = abs_key(P[r * kPST + c]);
+      if (v > best) { best = v; bi = r; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const T ob = __shfl_xor(best, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
+    __syncthreads();
+    best = redv[0];
+    bi = redi[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const T ob = redv[w];
+      const int oi = redi[w];
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    // R - (16k + c) >= 1 rows are active, so bi is a valid row; the clamp
+    // only guards the memory access.
+    const int pr = bi < R ? bi : R - 1;
+    const T pval = P[pr * kPST + c];
+    if (tid == 0) {
+      pv[c] = pr;
+      rst[pr] = k;
+      if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + c + 1;
+    }
+    const T inv = (pval != T(0)) ? T(1) / pval : T(0);
+    for (int r = tid; r < R; r += NT) {
+      if (r == pr || rst[r] != kInfoActive) continue;
+      const T l = P[r * kPST + c] * inv;
+      P[r * kPST + c] = l;
+      for (int cc = c + 1; cc < 16; ++cc) P[r * kPST + cc] -= l * P[pr * kPST + cc];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv, int *rstep,
                                                         int *info, int CH, Sel sel, BuildSrc bs) {
@@ -411,48 +464,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
       }
       __syncthreads();
     } else {
-      for (int c = 0; c < 16; ++c) {
-        T best = T(-1);
-        int bi = INT_MAX;
-        for (int r = tid; r < R; r += NT) {
-          if (rst[r] != kInfoActive) continue;
-          const T v = abs_key(P[r * kPST + c]);
-          if (v > best) { best = v; bi = r; }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const T ob = __shfl_xor(best, off);
-          const int oi = __shfl_xor(bi, off);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
-        __syncthreads();
-        best = redv[0];
-        bi = redi[0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) {
-          const T ob = redv[w];
-          const int oi = redi[w];
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        // R - (16k + c) >= 1 rows are active, so bi is a valid row; the clamp
-        // only guards the memory access.
-        const int pr = bi < R ? bi : R - 1;
-        const T pval = P[pr * kPST + c];
-        if (tid == 0) {
-          pv[c] = pr;
-          rst[pr] = k;
-          if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + c + 1;
-        }
-        const T inv = (pval != T(0)) ? T(1) / pval : T(0);
-        for (int r = tid; r < R; r += NT) {
-          if (r == pr || rst[r] != kInfoActive) continue;
-          const T l = P[r * kPST + c] * inv;
-          P[r * kPST + c] = l;
-          for (int cc = c + 1; cc < 16; ++cc) P[r * kPST + cc] -= l * P[pr * kPST + cc];
-        }
-        __syncthreads();
-      }
+      panel_wg<T, NT>(P, R, k, pv, rst, zeroPiv, redv, redi);
     }
 
     // L11^{-1} (unit lower triangular, rows in pivot order): column j of the
@@ -563,11 +575,6 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
   if (tid == 0) info[leaf] = *zeroPiv;
 }
 
-// Right-hand-side update of the triangular solves:  C -= A * Y for every
-// row tile with a qualifying row, where A = W[rows, panel k] (rows retired
-// after step k for the forward replay, before it for the back substitution;
-// other rows contribute zero) and Y the 16 solved rows in LDS.  Each wave
-// takes a row tile and up to four right-hand-side tiles at once.
 // ---------------------------------------------------------------------------
 // factor2: the same factorisation for R <= 256 with panels taken in pairs.
 // Panel A's update is applied at once only to panel B's column tile; panel
@@ -848,6 +855,209 @@ __global__ void __launch_bounds__(256, MINB) k_factor2_t(Geom g, T *M, int *piv,
     if (tid < 16) piv[(size_t)wi * R + k * 16 + tid] = pvA[tid];
     if (two && tid >= 16 && tid < 32) piv[(size_t)wi * R + (k + 1) * 16 + tid - 16] = pvB[tid - 16];
     __syncthreads();
+  }
+  for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
+  if (tid == 0) info[leaf] = *zeroPiv;
+}
+
+// ---------------------------------------------------------------------------
+// factorP: panels in pairs for R > 256 (up to p = 32), where two panels do
+// not fit LDS together.  Panel A is factored in the LDS panel buffer and
+// written back to the work matrix; A's update reaches panel B's column tile;
+// panel B is loaded into the same buffer and factored; the remaining columns
+// then take both updates in one pass, C -= L21_A U12_A + L21_B U12_B, with
+// L21_A read back from the work matrix (where it was just written, so
+// mostly from L2) and L21_B from LDS.  The trailing matrix thus streams
+// through HBM once per 32 columns instead of once per 16.  The stored form
+// is that of k_factor.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_factorP(Geom g, T *M, int *piv, int *rstep,
+                                                     int *info, int CH, Sel sel, BuildSrc bs) {
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  const int R = g.R, RT = g.RT, CT = g.CT;
+  const int UST = CH + 16;
+  T *P = (T *)smem;                       // [R][kPST]   current panel
+  T *U = P + (size_t)R * kPST;            // [32][UST]   U12 rows of A (0..15), B (16..31)
+  T *LA = U + 32 * UST;                   // [16][kPST]  L11_A^{-1}
+  T *LB = LA + 16 * kPST;                 // [16][kPST]  L11_B^{-1}
+  T *redv = LB + 16 * kPST;               // [NW]
+  int *rst = (int *)(redv + NW);          // [R]
+  int *tileAct = rst + R;                 // [RT]
+  int *pvA = tileAct + RT;                // [16]
+  int *pvB = pvA + 16;                    // [16]
+  int *redi = pvB + 16;                   // [NW]
+  int *zeroPiv = redi + NW;               // [1]
+  T *Ml = M + leaf_stride(g) * wi;
+  const LeafScale sc = leaf_scale(g, leaf);
+
+  for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
+  if (tid == 0) *zeroPiv = 0;
+  {
+    const size_t total = leaf_stride(g);
+    for (size_t e = tid; e < total; e += NT) {
+      const int tile = (int)(e >> 8);
+      int ri, ci;
+      Tile<T>::rc((int)(e & 255), ri, ci);
+      Ml[e] = (T)build_elem(g, sc, leaf, bs, (tile / CT) * 16 + ri, (tile % CT) * 16 + ci);
+    }
+  }
+  __syncthreads();
+
+  // factor the panel of column tile kk into P, L11^{-1} into Li, pivots into
+  // pv and the global pivot list, active row-tile flags; the factored panel
+  // is also written back to the work matrix
+  auto do_panel = [&](int kk, int *pv, T *Li) {
+    for (int e = tid; e < R * 16; e += NT) {
+      const int r = e >> 4, c = e & 15;
+      P[r * kPST + c] = Ml[tix<T>(r, kk * 16 + c, CT)];
+    }
+    __syncthreads();
+    panel_wg<T, NT>(P, R, kk, pv, rst, zeroPiv, redv, redi);
+    if (wv == 0 && lane < 16) {
+      const int j = lane;
+      T x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T acc = (i == j) ? T(1) : T(0);
+#pragma unroll
+        for (int q = 0; q < i; ++q) acc -= P[pv[i] * kPST + q] * x[q];
+        x[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Li[i * kPST + j] = x[i];
+      piv[(size_t)wi * R + kk * 16 + j] = pv[j];
+    }
+    for (int t = tid; t < RT; t += NT) {
+      int a = 0;
+      for (int q = 0; q < 16; ++q) a |= (rst[t * 16 + q] == kInfoActive);
+      tileAct[t] = a;
+    }
+    for (int e = tid; e < R * 16; e += NT) {
+      const int r = e >> 4, c = e & 15;
+      Ml[tix<T>(r, kk * 16 + c, CT)] = P[r * kPST + c];
+    }
+    __syncthreads();
+  };
+  // U12 rows over columns [c0, c0+cw): A's from its raw pivot rows, B's
+  // (two) from its raw pivot rows minus A's update at them; both written to
+  // U and into the pivot rows of W
+  auto u12 = [&](int k, int c0, int cw, bool two) {
+    const int nrow = two ? 32 : 16;
+    for (int e = tid; e < nrow * cw; e += NT) {
+      const int sr = e / cw, cc = e - sr * cw;
+      const int row = sr < 16 ? pvA[sr] : pvB[sr - 16];
+      U[sr * UST + cc] = Ml[tix<T>(row, c0 + cc, CT)];
+    }
+    __syncthreads();
+    for (int jl = wv; jl < (cw >> 4); jl += NW) {
+      const int cb = jl * 16 + (lane & 15);
+      typename Mfma<T>::acc ua = tri_apply<T>(LA, U, UST, jl * 16, lane);
+      wave_lds_fence<T>();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int sr = Tile<T>::crow(q, lane);
+        U[sr * UST + cb] = ua[q];
+        Ml[tix<T>(pvA[sr], c0 + cb, CT)] = ua[q];
+      }
+      if (two) {
+        wave_lds_fence<T>();
+        typename Mfma<T>::acc ub;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ub[q] = U[(16 + Tile<T>::crow(q, lane)) * UST + cb];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const T a = -Ml[tix<T>(pvB[lane & 15], k * 16 + 4 * kc + (lane >> 4), CT)];
+          const T b = U[(4 * kc + (lane >> 4)) * UST + cb];
+          ub = Mfma<T>::op(a, b, ub);
+        }
+        wave_lds_fence<T>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) U[(16 + Tile<T>::crow(q, lane)) * UST + cb] = ub[q];
+        wave_lds_fence<T>();
+        typename Mfma<T>::acc u2 = tri_apply<T>(LB, U + 16 * UST, UST, jl * 16, lane);
+        wave_lds_fence<T>();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int sr = Tile<T>::crow(q, lane);
+          U[(16 + sr) * UST + cb] = u2[q];
+          Ml[tix<T>(pvB[sr], c0 + cb, CT)] = u2[q];
+        }
+      }
+    }
+    __syncthreads();
+  };
+  // C -= L21_A U12_A (+ L21_B U12_B) on the active row tiles over columns
+  // [c0, c0+cw); L21_A from the work matrix when two, else from P
+  auto trailing = [&](int k, int c0, int cw, bool two) {
+    const int ntj = cw >> 4;
+    const int nstrip = (ntj + 3) >> 2;
+    for (int t = wv; t < RT * nstrip; t += NW) {
+      const int ti = t / nstrip, j0 = (t - ti * nstrip) * 4;
+      if (!tileAct[ti]) continue;
+      const int nj = min(4, ntj - j0);
+      T *Ct = Ml + ((size_t)(ti * CT + (c0 >> 4) + j0) << 8);
+      typename Mfma<T>::acc acc[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[jj][q] = Ct[jj * 256 + q * 64 + lane];
+        }
+      }
+      const int ar = ti * 16 + (lane & 15);
+      const bool act = rst[ar] == kInfoActive;
+      // one 16-deep update at a time: L21 from the work matrix (panel A of
+      // a pair) or from P (the last panel taken)
+      for (int h = two ? 0 : 1; h < 2; ++h) {
+        T a[4];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const int ac = 4 * kc + (lane >> 4);
+          a[kc] = act ? -(h == 0 ? Ml[tix<T>(ar, k * 16 + ac, CT)] : P[ar * kPST + ac]) : T(0);
+        }
+        const T *Uh = U + (two && h == 1 ? 16 * UST : 0);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          if (jj < nj) {
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+              const T b = Uh[(4 * kc + (lane >> 4)) * UST + (j0 + jj) * 16 + (lane & 15)];
+              acc[jj] = Mfma<T>::op(a[kc], b, acc[jj]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        if (jj < nj) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Ct[jj * 256 + q * 64 + lane] = acc[jj][q];
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  const int cend = CT * 16;
+  for (int k = 0; k < RT; k += 2) {
+    const bool two = k + 1 < RT;
+    do_panel(k, pvA, LA);
+    if (two) {
+      // panel A's update of panel B's column tile (P still holds panel A)
+      u12(k, 16 * (k + 1), 16, false);
+      trailing(k, 16 * (k + 1), 16, false);
+      do_panel(k + 1, pvB, LB);
+    }
+    for (int c0 = 16 * (k + (two ? 2 : 1)); c0 < cend; c0 += CH) {
+      const int cw = min(CH, cend - c0);
+      u12(k, c0, cw, two);
+      trailing(k, c0, cw, two);
+    }
   }
   for (int r = tid; r < R; r += NT) rstep[(size_t)wi * R + r] = rst[r];
   if (tid == 0) info[leaf] = *zeroPiv;
@@ -1953,6 +2163,58 @@ hipError_t launch_factor2(const Geom &g, int nleaf, T *M, int *piv, int *rstep, 
   return hipGetLastError();
 }
 
+template <typename T>
+size_t factorP_lds(const Geom &g, int CH) {
+  constexpr int NW = 512 / 64;
+  size_t b = sizeof(T) * ((size_t)g.R * kPST + 32 * (size_t)(CH + 16) + 32 * kPST + NW);
+  b += sizeof(int) * ((size_t)g.R + g.RT + 32 + NW + 1);
+  return b;
+}
+
+// Column chunk of factorP: 128 columns if two workgroups then fit on a CU,
+// else 64.  Each wavefront of the trailing pass takes strips of four column
+// tiles, so chunks that are not a multiple of 64 leave a short strip per row
+// tile that reloads the whole L21 operand (measured 10-20% slower).
+template <typename T>
+int pick_chP(const Geom &g) {
+  const int full = g.CT * 16;
+  if (g.tune_ch > 0) {
+    const int c = g.tune_ch < full ? g.tune_ch : full;
+    if (factorP_lds<T>(g, c) <= kLdsLimit) return c;
+  }
+  const int c128 = full < 128 ? full : 128, c64 = full < 64 ? full : 64;
+  if (factorP_lds<T>(g, c128) <= kLdsLimit / 2) return c128;
+  if (factorP_lds<T>(g, c64) <= kLdsLimit) return c64;
+  for (int ch = 48; ch >= 16; ch -= 16) {
+    const int c = ch < full ? ch : full;
+    if (factorP_lds<T>(g, c) <= kLdsLimit) return c;
+  }
+  return 0;
+}
+
+// Two workgroups of 512 per CU need four wavefronts per SIMD (at most 128
+// registers each) and half the LDS; the one-per-CU instance may use more
+// registers.
+template <typename T>
+hipError_t launch_factorP(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
+                          const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  const int ch = pick_chP<T>(g);
+  if (!ch) return hipErrorInvalidValue;
+  const size_t lds = factorP_lds<T>(g, ch);
+  if (2 * lds <= kLdsLimit) {
+    hipError_t e = set_lds(k_factorP<T, 512, 4>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_factorP<T, 512, 4>), dim3(nleaf), dim3(512), lds, s, g, M, piv, rstep,
+                       info, ch, sel, bs);
+    return hipGetLastError();
+  }
+  hipError_t e = set_lds(k_factorP<T, 512, 2>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_factorP<T, 512, 2>), dim3(nleaf), dim3(512), lds, s, g, M, piv, rstep, info,
+                     ch, sel, bs);
+  return hipGetLastError();
+}
+
 template <int RT, int NW, int NS>
 hipError_t launch_rr(const Geom &g, int nleaf, float *M, int *piv, int *rstep, int *info,
                      const BuildSrc &bs, hipStream_t s, const Sel &sel) {
@@ -2004,6 +2266,13 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
   if (pairs) {
     if (fp32) return launch_factor2<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     return launch_factor2<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
+  }
+  // FP32 work matrices below 400 rows run two single-panel workgroups per CU
+  // without spills and gain nothing from pairs (measured at p = 19, 20)
+  if (g.R > 256 && factor_pairs_enabled() &&
+      (g.tune_variant == 2 || (g.tune_variant == 0 && (!fp32 || g.R >= 400)))) {
+    if (fp32) return launch_factorP<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
+    return launch_factorP<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
   }
   if (fp32) {
     const int ch = pick_ch<float>(g);

@@ -3,7 +3,8 @@
 For every order group of a batch it times the candidate settings of
 `hps_batch_set_tuning` -- the factorisation variant (one 16-column panel per
 trailing pass, panels in pairs, or for FP32 and p <= 16 the work matrix held
-in registers) and the column chunk of the U12 / trailing passes -- on a batch of that group's own leaves, keeps the fastest, applies
+in registers) and the column chunk of the U12 / trailing passes -- on a batch
+of that group's own leaves, keeps the fastest, applies
 it to the batch, and remembers it in a JSON cache keyed by
 ``p<order>_<precision>_L<leaf-count bucket>``.  Timing uses the library's
 per-phase HIP events (`hps_ctx_phase_times`).
@@ -33,13 +34,18 @@ def cache_key(p: int, prec: int, nleaf: int) -> str:
 
 def candidates(p: int, prec: int = hps.HPS_FP64) -> List[Tuple[int, int]]:
     """(variant, chunk_cols) pairs worth timing for order p: the streaming
-    variants over their column chunks, and for FP32 work matrices of at most
-    208 rows the register-resident variant (which has no chunk)."""
+    variants over their column chunks (the paired one of large work matrices
+    only at 64 and 128 columns), and for FP32 work matrices of at most 208
+    rows the register-resident variant (which has no chunk)."""
     ni, nb = (p - 2) ** 2, 4 * (p - 2)
     cols = ((ni + 15) // 16) * 16 + ((nb + 1 + 15) // 16) * 16
     chunks = [c for c in (32, 64, 128, 256, 512) if c < cols] + [0]
-    variants = [1, 2] if ni <= 256 else [1]
-    out = [(v, c) for v in variants for c in chunks]
+    if ni <= 256:
+        out = [(v, c) for v in (1, 2) for c in chunks]
+    else:
+        # paired panels with a large work matrix: only strips of whole
+        # four-tile groups pay (64 or 128 columns)
+        out = [(1, c) for c in chunks] + [(2, c) for c in (64, 128) if c < cols] + [(2, 0)]
     if prec == hps.HPS_FP32_REFINE and ((ni + 15) // 16) * 16 <= 208:
         out.append((3, 0))
     return out

@@ -151,6 +151,49 @@ def test_condense_fp32_register_resident(torch, p):
     B.close()
 
 
+# Work matrices above 256 rows: panels in pairs with the first panel's
+# multipliers re-read from the work matrix (variant 2), at both occupancies
+# (64 and 128 column chunks select one or two workgroups per CU), with an
+# even and an odd number of row tiles (p = 23: 28 tiles; p = 20, 32: odd),
+# and the single-panel variant on an even tile count.
+@pytest.mark.parametrize("p,prec,variant,chunk", [
+    (23, hps.HPS_FP64, 2, 0), (23, hps.HPS_FP32_REFINE, 2, 0), (20, hps.HPS_FP64, 2, 64),
+    (20, hps.HPS_FP32_REFINE, 2, 0), (32, hps.HPS_FP32_REFINE, 2, 128), (32, hps.HPS_FP64, 2, 64),
+    (26, hps.HPS_FP64, 1, 0)])
+def test_condense_large_factor_variants(torch, p, prec, variant, chunk):
+    _say(f"condense large p={p} prec={prec} variant={variant} chunk={chunk}")
+    prob = _small(p, 2)
+    B = _batch([prob])
+    hps.hps_batch_set_tuning(B.batch, 0, variant, chunk)
+    S, w, info, st = B.condense(prec=prec, max_refine=3, sync=True)
+    assert st == hps.HPS_OK and bool((info == 0).all())
+    Xt, _ = B.export()
+    nb, ni = 4 * (p - 2), (p - 2) ** 2
+    Sg, Xg = S.view(-1, nb, nb).cpu().numpy(), Xt.view(-1, nb, ni).cpu().numpy()
+    tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+    for t in range(prob.nleaf):
+        bl, c = oracle_leaf(prob, t)
+        bar = leaf_bar(bl.Aii, tol)
+        assert relerr(Sg[t], c.S) <= bar, t
+        assert relerr(Xg[t].T, c.X) <= (bar if prec == hps.HPS_FP64 else max(bar, 1e-8)), t
+    B.close()
+    # with the body-load column
+    fp = _forced_problem(p)
+    B = _batch([fp])
+    hps.hps_batch_set_tuning(B.batch, 0, variant, chunk)
+    f = B.interior_f()
+    S, w, info, st = B.condense(prec=prec, f=f, max_refine=3, sync=True)
+    assert st == hps.HPS_OK
+    _, h = B.export()
+    Sg, wg, hg = (S.view(-1, nb, nb).cpu().numpy(), w.view(-1, nb).cpu().numpy(),
+                  h.view(-1, ni).cpu().numpy())
+    for t in range(fp.nleaf):
+        bl, c = oracle_leaf(fp, t, oracle_interior_f(fp, t))
+        bar = leaf_bar(bl.Aii, tol)
+        assert relerr(Sg[t], c.S) <= bar and relerr(wg[t], c.w) <= bar and relerr(hg[t], c.h) <= bar
+    B.close()
+
+
 @pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
 def test_annulus_variable_coefficients(torch, prec):
     _say(f"annulus prec={prec}")

@@ -18,10 +18,9 @@ def test_candidates_respect_kernel_limits():
         ni = (p - 2) ** 2
         for v, c in cands:
             assert v in (1, 2) and c % 16 == 0 and 0 <= c <= 1024
-            if v == 2:
-                assert ni <= 256
-    assert any(v == 2 for v, _ in tune.candidates(16))
-    assert all(v == 1 for v, _ in tune.candidates(20))
+            if v == 2 and ni > 256:
+                assert c in (0, 64, 128)
+        assert any(v == 1 for v, _ in cands) and any(v == 2 for v, _ in cands)
 
 
 def test_register_resident_candidate_only_for_small_fp32():
