@@ -1714,6 +1714,241 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
 }
 
 // ---------------------------------------------------------------------------
+// Triangular solves for work matrices of at most 256 rows with the
+// right-hand sides held in registers.  Row tile i of the right-hand sides
+// (all its column tiles, in pivot (step) order) lives in the FP64 MFMA
+// accumulators of wavefront i mod NW for the whole solve.  The 16 x 16
+// diagonal blocks of the factors are inverted once per leaf into LDS (one
+// column per thread), so every step of the block substitution is a tile
+// product:
+//   forward   Y_k = L_kk^{-1} (R_k - sum_{j<k} L_kj Y_j)
+//   backward  X_k = U_kk^{-1} (Y_k - sum_{j>k} U_kj X_j)
+// where L_kj / U_kj is tile j of the 16 pivot rows of panel k.  Step k: the
+// owner of row tile k forms Y_k / X_k and publishes it in LDS; after one
+// barrier every wavefront applies it to its own row tiles.  Each factor tile
+// is thus read once per leaf (by the wavefront owning its row tile) and used
+// for every column tile, and the tiles of step k-1 are loaded while step k
+// runs.  The right-hand sides are read once and the solution written once.
+// PASSES: 1 backward only, 3 forward then backward.  RTM bounds RT and NCTM
+// the number of right-hand-side column tiles (register arrays are indexed
+// statically).
+// ---------------------------------------------------------------------------
+constexpr int kDST = 17;   // LDS row stride of the diagonal blocks
+
+// Workgroup barrier ordering LDS accesses only: global loads still in flight
+// (the next step's prefetched operands) are not waited for, as they would be
+// by __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
+__global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, const int *piv,
+                                                      BackOut o, Sel sel) {
+  constexpr int NT = 64 * NW, RPW = (RTM + NW - 1) / NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  if (o.skip && o.skip[leaf]) return;
+  const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
+  double *red = (double *)smem;                         // [NW]
+  double *xb = red + 8;                                 // [2][NCTM][256] published Y_k / X_k
+  T *D = (T *)(xb + 2 * NCTM * 256);                    // [RT][16][kDST]
+  int *pva = (int *)(D + (size_t)RT * 16 * kDST);       // [R] pivot rows in step order
+  const T *Ml = M + leaf_stride(g) * wi;
+  for (int r = tid; r < R; r += NT) pva[r] = min(max(piv[(size_t)wi * R + r], 0), R - 1);
+  __syncthreads();
+  // diagonal block b: element (s, q) = W[pivot row of step 16b+s][16b+q]
+  for (int e = tid; e < RT * 256; e += NT) {
+    const int b = e >> 8, s = (e >> 4) & 15, q = e & 15;
+    D[(b * 16 + s) * kDST + q] = Ml[tix<T>(pva[16 * b + s], 16 * b + q, CT)];
+  }
+  __syncthreads();
+  // invert in place, column j of block b per thread, whole blocks per round:
+  // L_bb^{-1} (unit lower) strictly below the diagonal, then U_bb^{-1} on and
+  // above it (each inverse reads only its own triangle of the block)
+  for (int base = 0; base < RT * 16; base += NT) {
+    const int t = base + tid, b = t >> 4, j = t & 15;
+    const bool mine = t < RT * 16;
+    T *Db = D + (mine ? b : 0) * 16 * kDST;
+    if (PASSES & 2) {
+      double zl[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) acc -= (double)Db[i * kDST + q] * zl[q];
+        zl[i] = acc;
+      }
+      __syncthreads();
+      if (mine) {
+#pragma unroll
+        for (int i = 1; i < 16; ++i)
+          if (i > j) Db[i * kDST + j] = (T)zl[i];
+      }
+    }
+    double zu[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = i + 1; q < 16; ++q) acc -= (double)Db[i * kDST + q] * zu[q];
+      zu[i] = (i <= j) ? acc / (double)Db[i * kDST + i] : 0.0;
+    }
+    __syncthreads();
+    if (mine) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i <= j) Db[i * kDST + j] = (T)zu[i];
+    }
+    __syncthreads();
+  }
+
+  const int cl = lane & 15, rq = lane >> 4;
+  // this wavefront's row tiles i = li*NW + wv, gathered in step order
+  d4 y[RPW][NCTM];
+#pragma unroll
+  for (int li = 0; li < RPW; ++li) {
+    const int i = li * NW + wv;
+#pragma unroll
+    for (int c = 0; c < NCTM; ++c) {
+      if (i < RT && c < NCT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          y[li][c][q] = (double)Ml[tix<T>(pva[16 * i + 4 * q + rq], R + 16 * c + cl, CT)];
+      }
+    }
+  }
+  // factor operand of row tile i at step k: A[r][4kc + rq] = W[pivot of 16i + r][16k + 4kc + rq],
+  // kept raw (no conversion or select) so that nothing waits for the loads
+  // before the step that uses them; addresses are clamped into the leaf
+  auto load_a = [&](T (&a)[RPW][4], int k) __attribute__((always_inline)) {
+    const int kk = min(max(k, 0), RT - 1);
+#pragma unroll
+    for (int li = 0; li < RPW; ++li) {
+      const int pr = pva[16 * min(li * NW + wv, RT - 1) + cl];
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) a[li][kc] = Ml[tix<T>(pr, 16 * kk + 4 * kc + rq, CT)];
+    }
+  };
+  double nd = 0.0;
+  // the owner of row tile k applies the inverted diagonal block to it,
+  // publishes the result in LDS and (backward) writes it out
+  auto form = [&](int k, bool fwd) __attribute__((always_inline)) {
+    const T *Db = D + k * 16 * kDST;
+    double *xk = xb + (k & 1) * NCTM * 256;
+#pragma unroll
+    for (int li = 0; li < RPW; ++li) {
+      if (li * NW + wv != k) continue;
+#pragma unroll
+      for (int c = 0; c < NCTM; ++c) {
+        if (c >= NCT) continue;
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          const int cc = 4 * kc + rq;
+          const double dv = (double)Db[cl * kDST + cc];
+          const double av = fwd ? (cl > cc ? dv : (cl == cc ? 1.0 : 0.0)) : (cl <= cc ? dv : 0.0);
+          z = mfma64(av, y[li][c][kc], z);
+        }
+        y[li][c] = z;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xk[(c * 4 + q) * 64 + lane] = z[q];
+        const int col = 16 * c + cl;
+        if (fwd || col >= g.nrhs) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ii = 16 * k + 4 * q + rq;
+          if (ii >= ni) continue;
+          const double v = z[q];
+          if (o.mode == BACK_UI) {
+            o.ui[(size_t)leaf * ni + ii] = v;
+          } else {
+            double *dst = (col < nb) ? o.Xt + ((size_t)leaf * nb + col) * ni + ii
+                                     : o.h + (size_t)leaf * ni + ii;
+            if (o.mode == BACK_STORE) {
+              *dst = v;
+            } else {
+              *dst += v;
+              nd += v * v;
+            }
+          }
+        }
+      }
+    }
+  };
+  // step k: everyone applies the published Y_k / X_k to their own row tiles
+  // (with the operands loaded one step earlier); the owner of the next row
+  // tile, whose last update this was, forms and publishes it before the
+  // barrier, so that forming is off the other wavefronts' path
+  auto step = [&](int k, bool fwd, const T (&a)[RPW][4]) __attribute__((always_inline)) {
+    const double *xk = xb + (k & 1) * NCTM * 256;
+#pragma unroll
+    for (int li = 0; li < RPW; ++li) {
+      const int i = li * NW + wv;
+      if (i >= RT || (fwd ? i <= k : i >= k)) continue;
+#pragma unroll
+      for (int c = 0; c < NCTM; ++c) {
+        if (c >= NCT) continue;
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          y[li][c] = mfma64((double)a[li][kc], -xk[(c * 4 + kc) * 64 + lane], y[li][c]);
+      }
+    }
+    const int kn = fwd ? k + 1 : k - 1;
+    if (kn >= 0 && kn < RT) form(kn, fwd);
+    lds_barrier();
+  };
+  T a0[RPW][4], a1[RPW][4];
+  if (PASSES & 2) {
+    load_a(a0, 0);
+    form(0, true);
+    lds_barrier();
+#pragma unroll 1
+    for (int k = 0; k < RT; k += 2) {
+      load_a(a1, k + 1);
+      step(k, true, a0);
+      if (k + 1 < RT) {
+        load_a(a0, k + 2);
+        step(k + 1, true, a1);
+      }
+    }
+  }
+  // backward; X_k is written out by its owner when formed
+  load_a(a0, RT - 1);
+  form(RT - 1, false);
+  lds_barrier();
+#pragma unroll 1
+  for (int kk = 0; kk < RT; kk += 2) {
+    const int k = RT - 1 - kk;
+    load_a(a1, k - 1);
+    step(k, false, a0);
+    if (k - 1 >= 0) {
+      load_a(a0, k - 2);
+      step(k - 1, false, a1);
+    }
+  }
+  if (o.mode == BACK_ACCUM) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
+    if (lane == 0) red[wv] = nd;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[w];
+      o.norms[kNormStride * (size_t)leaf + 16] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 refinement residual  r = A_ib - A_ii X  (and f_i - A_ii h), applied
 // through the tensor structure of the collocation operator: each interior
 // row couples only to its own x1-line and x2-line of nodes.  One workgroup
@@ -2344,14 +2579,70 @@ hipError_t launch_trisolve(const Geom &g, int nleaf, T *M, const int *piv, const
   return hipGetLastError();
 }
 
+// HPS_SOLVE_RR=0 turns the register-resident solves off.
+bool solve_rr_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("HPS_SOLVE_RR");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
+// The register-resident solves cover work matrices of at most 256 rows with
+// at most five right-hand-side column tiles (every order p <= 18).
+bool solve_rr_applies(const Geom &g) {
+  const int nct = g.CT - g.RT;
+  return solve_rr_enabled() && g.R <= 256 && nct >= 1 && nct <= 5;
+}
+
+template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
+hipError_t launch_solve_rr_t(const Geom &g, int nleaf, const T *M, const int *piv,
+                             const BackOut &o, hipStream_t s, const Sel &sel) {
+  if (g.RT > RTM || g.CT - g.RT > NCTM) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * (8 + 2 * NCTM * 256) +
+                     sizeof(T) * (size_t)g.RT * 16 * kDST + sizeof(int) * (size_t)g.R;
+  hipError_t e = set_lds(k_solve_rr<T, RTM, NCTM, NW, MINW, PASSES>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve_rr<T, RTM, NCTM, NW, MINW, PASSES>), dim3(nleaf), dim3(64 * NW), lds,
+                     s, g, M, piv, o, sel);
+  return hipGetLastError();
+}
+
+// Up to 8 row tiles: four wavefronts, four per SIMD.  More: the FP64
+// back substitution keeps four wavefronts (four row tiles each, up to 232
+// registers, two wavefronts per SIMD), the FP32 solves take eight (at most
+// 128 registers, four per SIMD); measured at p = 16 and 18.
+template <typename T, int PASSES>
+hipError_t launch_solve_rr(const Geom &g, int nleaf, const T *M, const int *piv, const BackOut &o,
+                           hipStream_t s, const Sel &sel) {
+  if (!solve_rr_applies(g)) return hipErrorNotSupported;
+  constexpr bool wide = !(std::is_same<T, double>::value && PASSES == 1);
+  constexpr int NW = wide ? 8 : 4, MW = wide ? 4 : 2;
+  const int nct = g.CT - g.RT;
+  if (g.RT <= 4 && nct <= 4)
+    return launch_solve_rr_t<T, 4, 4, 4, 4, PASSES>(g, nleaf, M, piv, o, s, sel);
+  if (g.RT <= 8 && nct <= 4)
+    return launch_solve_rr_t<T, 8, 4, 4, 4, PASSES>(g, nleaf, M, piv, o, s, sel);
+  if (nct <= 4) return launch_solve_rr_t<T, 16, 4, NW, MW, PASSES>(g, nleaf, M, piv, o, s, sel);
+  return launch_solve_rr_t<T, 16, 5, NW, MW, PASSES>(g, nleaf, M, piv, o, s, sel);
+}
+
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
+  if (solve_rr_applies(g)) {
+    if (fp32) return launch_solve_rr<float, 1>(g, nleaf, (const float *)M, piv, o, s, sel);
+    return launch_solve_rr<double, 1>(g, nleaf, (const double *)M, piv, o, s, sel);
+  }
   if (fp32) return launch_trisolve<float, 1>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
   return launch_trisolve<double, 1>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
 }
 
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
                                const int *rstep, const BackOut &o, int nch, hipStream_t s) {
+  if (solve_rr_applies(g)) {
+    if (nch != 1) return hipErrorInvalidValue;
+    return launch_solve_rr<float, 3>(g, nleaf, (const float *)M, piv, o, s, Sel());
+  }
   return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel(), nch);
 }
 
@@ -2360,9 +2651,10 @@ hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv
 // re-read the factors); later ones are left with the few leaves still
 // refining, so their columns are split over up to four workgroups (the
 // chunk count is the number of 16-column tiles the solve splits into, at
-// most four).
+// most four).  The register-resident solves already spread a leaf's column
+// tiles over the wavefronts of its one workgroup.
 int refine_chunks(const Geom &g, int it) {
-  if (it <= 1) return 1;
+  if (it <= 1 || solve_rr_applies(g)) return 1;
   const int tiles = (g.CT * 16 - g.R) / 16;
   const int per = (tiles + kMaxChunks - 1) / kMaxChunks;   // tiles per chunk
   return (tiles + per - 1) / per;
