@@ -2063,6 +2063,141 @@ __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const doubl
   }
 }
 
+// The same residual for leaves with at most 16 interior nodes per line
+// (p <= 18).  Each thread forms its row's 2m line weights once per leaf, in
+// registers (lines padded to 16 nodes with zero weights), and every staged
+// column is laid out twice in LDS, by x1-lines and by x2-lines (18-double
+// row stride, so that the lines of a wavefront's rows fall on different
+// banks), so that both line sums of a row read contiguous 128-bit words.
+template <int CW>
+__global__ void __launch_bounds__(256) k_residual_l(Geom g, float *M32, const double *Xt,
+                                                    const double *h, const double *f,
+                                                    const int *skip, double *norms) {
+  constexpr int NT = 256, LS = 18;
+  __shared__ __align__(16) double xl[CW][16 * LS];   // [c][j-1][k-1] = x(k, j): x1-lines
+  __shared__ __align__(16) double yl[CW][16 * LS];   // [c][i-1][k-1] = x(i, k): x2-lines
+  __shared__ double red[NT / 64][2];
+  __shared__ double sD[18 * 18], sD2[18 * 18];
+  const int leaf = blockIdx.x;
+  if (skip && skip[leaf]) return;
+  stage_tables(g, sD, sD2);
+  __syncthreads();
+  const LeafScale sc = leaf_scale(g, leaf);
+  const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R, CT = g.CT;
+  float *Ml = M32 + leaf_stride(g) * leaf;
+  const int ncol = (h && f) ? nb + 1 : nb;
+  const int r = threadIdx.x;   // this thread's row
+  int i = 1, j = 1;
+  double kb = 0.0, bw0 = 0.0, bw1 = 0.0, bs0 = 0.0, bs1 = 0.0;
+  double wx[16], wy[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) wx[k] = wy[k] = 0.0;
+  if (r < ni) {
+    i = r % m + 1;
+    j = r / m + 1;
+    const size_t n = (size_t)leaf * p * p + i + (size_t)p * j;
+    const double ax2 = (g.a11 ? g.a11[n] : 1.0) * sc.sx * sc.sx;
+    const double ax1 = (g.c1 ? g.c1[n] : 0.0) * sc.sx;
+    const double ay2 = (g.a22 ? g.a22[n] : 1.0) * sc.sy * sc.sy;
+    const double ay1 = (g.c2 ? g.c2[n] : 0.0) * sc.sy;
+    kb = g.k2b ? g.k2b[n] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      if (k < m) {
+        wx[k] = ax2 * sD2[i * p + k + 1] + ax1 * sD[i * p + k + 1];
+        wy[k] = ay2 * sD2[j * p + k + 1] + ay1 * sD[j * p + k + 1];
+      }
+    }
+    bw0 = -(ax2 * sD2[i * p] + ax1 * sD[i * p]);
+    bw1 = -(ax2 * sD2[i * p + p - 1] + ax1 * sD[i * p + p - 1]);
+    bs0 = -(ay2 * sD2[j * p] + ay1 * sD[j * p]);
+    bs1 = -(ay2 * sD2[j * p + p - 1] + ay1 * sD[j * p + p - 1]);
+  }
+  // the padding of the lines is never written by the staging below
+  for (int e = threadIdx.x; e < CW * 16 * LS; e += NT) {
+    (&xl[0][0])[e] = 0.0;
+    (&yl[0][0])[e] = 0.0;
+  }
+  double nr = 0.0, nx = 0.0;
+  const int ngrp = (ncol + CW - 1) / CW;
+  const int g0 = (ngrp * (int)blockIdx.y) / (int)gridDim.y;
+  const int g1 = (ngrp * ((int)blockIdx.y + 1)) / (int)gridDim.y;
+  for (int c0 = g0 * CW; c0 < min(g1 * CW, ncol); c0 += CW) {
+    const int cw = min(CW, ncol - c0);
+    __syncthreads();
+    // each thread stages its own row of the chunk's columns (coalesced)
+    if (r < ni) {
+#pragma unroll
+      for (int c = 0; c < CW; ++c) {
+        if (c >= cw) continue;
+        const int col = c0 + c;
+        const double v = (col < nb) ? Xt[((size_t)leaf * nb + col) * ni + r] : h[(size_t)leaf * ni + r];
+        xl[c][(j - 1) * LS + i - 1] = v;
+        yl[c][(i - 1) * LS + j - 1] = v;
+      }
+    }
+    __syncthreads();
+    if (r >= ni) {
+      if (r < R)
+        for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = 0.0f;
+      continue;
+    }
+    float out[CW];
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+      out[c] = 0.0f;
+      if (c >= cw) continue;
+      const double *xr = &xl[c][(j - 1) * LS];
+      const double *yr = &yl[c][(i - 1) * LS];
+      const double x = xr[i - 1];
+      // -(A_ii x) = k2b x + sum over both lines of (a d2 + c d1) x
+      double acc = kb * x;
+#pragma unroll
+      for (int k = 0; k < 16; k += 2) {
+        const double2 a = *(const double2 *)(xr + k);
+        const double2 b = *(const double2 *)(yr + k);
+        acc += wx[k] * a.x + wx[k + 1] * a.y + wy[k] * b.x + wy[k + 1] * b.y;
+      }
+      const int col = c0 + c;
+      double bval = 0.0;   // entry of [A_ib f] in this row
+      if (col == nb) bval = f[(size_t)leaf * ni + r];
+      else if (col == j - 1) bval = bw0;
+      else if (col == m + j - 1) bval = bw1;
+      else if (col == 2 * m + i - 1) bval = bs0;
+      else if (col == 3 * m + i - 1) bval = bs1;
+      const double res = bval + acc;
+      nr += res * res;
+      nx += x * x;
+      out[c] = (float)res;
+    }
+    // the chunk's CW columns of this row are contiguous in its work-matrix
+    // tile (chunks start at multiples of CW, CW divides 16)
+    if (cw == CW) {
+      float4 *dst = (float4 *)(Ml + tix<float>(r, R + c0, CT));
+#pragma unroll
+      for (int q = 0; q < CW / 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+    } else {
+      for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = out[c];
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    nr += __shfl_xor(nr, off);
+    nx += __shfl_xor(nx, off);
+  }
+  if (lane == 0) {
+    red[wv][0] = nr;
+    red[wv][1] = nx;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double a = 0.0;
+    for (int w = 0; w < NT / 64; ++w) a += red[w][threadIdx.x];
+    norms[kNormStride * (size_t)leaf + 8 + 4 * threadIdx.x + blockIdx.y] = a;
+  }
+}
+
 // Stop test of the refinement, per leaf, after the residual r_k of X_k: the
 // estimated forward error rho ||dX_k|| is at most tol ||X_k||, where dX_k is
 // the last correction and rho, the contraction factor of the iteration, is
@@ -2560,6 +2695,12 @@ hipError_t launch_residual_t(const Geom &g, int nleaf, float *M32, const double 
 hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *Xt,
                            const double *h, const double *f, const int *skip, double *norms,
                            int nch, hipStream_t s) {
+  if (g.m <= 16 && g.R <= 256) {
+    if (nch < 1 || nch > kMaxChunks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_residual_l<4>), dim3(nleaf, nch), dim3(256), 0, s, g, M32, Xt, h, f,
+                       skip, norms);
+    return hipGetLastError();
+  }
   if (g.R <= 256) return launch_residual_t<256, 8>(g, nleaf, M32, Xt, h, f, skip, norms, nch, s);
   return launch_residual_t<1024, 8>(g, nleaf, M32, Xt, h, f, skip, norms, nch, s);
 }
