@@ -29,13 +29,20 @@ import time
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
-# Calibrated HBM traffic of one k_factor launch on this workload, from
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (KiB per dispatch, FETCH scaled by
-# 2.0 and WRITE by 1.0 against a 1 GiB device copy), keyed by the sha256
-# prefix of the kernel source it was measured on.
+# Calibrated HBM traffic of one factorisation launch, from rocprofv3 --pmc
+# FETCH_SIZE / WRITE_SIZE (KiB per dispatch, FETCH scaled by 2.0 and WRITE by
+# 1.0 against a 1 GiB device copy), keyed by the sha256 prefix of the kernel
+# source it was measured on, the workload and the precision.
 MEASURED_TRAFFIC = {
-    ("150ecf31788da341", "fp64"): {"fetch_bytes": 3007533.625 * 2.0 * 1024,
-                                   "write_bytes": 8168767.813 * 1.0 * 1024},
+    ("7676dd3afc7a27ca", "bump_64x64_p16", "fp64"): {
+        "kernel": "k_factor2_t<double, 2>",
+        "fetch_bytes": 3005674.104 * 2.0 * 1024, "write_bytes": 8168235.490 * 1.0 * 1024},
+    ("7676dd3afc7a27ca", "bump_64x64_p16", "fp32"): {
+        "kernel": "k_factor2_t<float, 3>",
+        "fetch_bytes": 1482952.438 * 2.0 * 1024, "write_bytes": 4122218.312 * 1.0 * 1024},
+    ("7676dd3afc7a27ca", "bumps_32x32_p32", "fp64"): {
+        "kernel": "k_factorP<double, 512, 2>",
+        "fetch_bytes": 51464702.250 * 2.0 * 1024, "write_bytes": 93055172.969 * 1.0 * 1024},
 }
 
 
@@ -288,14 +295,15 @@ def main() -> int:
         achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
         line["phases_ms_per_step"] = {k: v[0] / args.steps for k, v in phases.items() if v[1]}
         # every tile product runs on the FP64 MFMA in both precisions
-        line["roofline"] = {"bound": "mfma", "kernel": "k_factor", "achieved": achieved,
+        line["roofline"] = {"bound": "mfma", "kernel": "factorisation", "achieved": achieved,
                             "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                             "traffic": None,
                             "per_launch_flop": fl["factor"] * L * args.steps / max(f_n, 1),
                             "launch_ms": f_ms / max(f_n, 1),
                             "launches_per_step": f_n / args.steps}
-        tr = MEASURED_TRAFFIC.get((kernel_source_hash(), prec_name))
+        tr = MEASURED_TRAFFIC.get((kernel_source_hash(), line["config"]["workload"], prec_name))
         if tr is not None:
+            line["roofline"]["kernel"] = tr["kernel"]
             line["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
             line["roofline"]["traffic_detail"] = dict(tr, unit="bytes per launch",
                                                       source="rocprofv3 --pmc, calibrated")
