@@ -1748,22 +1748,15 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
-__global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, const int *piv,
-                                                      BackOut o, Sel sel) {
-  constexpr int NT = 64 * NW, RPW = (RTM + NW - 1) / NW;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int leaf;
-  if (!resolve_leaf(sel, leaf)) return;
-  if (o.skip && o.skip[leaf]) return;
-  const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
-  double *red = (double *)smem;                         // [NW]
-  double *xb = red + 8;                                 // [2][NCTM][256] published Y_k / X_k
-  T *D = (T *)(xb + 2 * NCTM * 256);                    // [RT][16][kDST]
-  int *pva = (int *)(D + (size_t)RT * 16 * kDST);       // [R] pivot rows in step order
-  const T *Ml = M + leaf_stride(g) * wi;
-  for (int r = tid; r < R; r += NT) pva[r] = min(max(piv[(size_t)wi * R + r], 0), R - 1);
+// Pivot list of the leaf (clamped into it) and the inverted 16 x 16
+// diagonal blocks of its factors, into LDS; the whole workgroup takes part.
+// Block b holds L_bb^{-1} (unit lower) strictly below the diagonal (forward
+// pass only) and U_bb^{-1} on and above it.
+template <typename T, int PASSES>
+__device__ __forceinline__ void stage_inverse_diag(const Geom &g, const T *Ml, const int *pivl,
+                                                   T *D, int *pva, int tid, int NT) {
+  const int R = g.R, RT = g.RT, CT = g.CT;
+  for (int r = tid; r < R; r += NT) pva[r] = min(max(pivl[r], 0), R - 1);
   __syncthreads();
   // diagonal block b: element (s, q) = W[pivot row of step 16b+s][16b+q]
   for (int e = tid; e < RT * 256; e += NT) {
@@ -1810,6 +1803,25 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
     }
     __syncthreads();
   }
+
+}
+
+template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
+__global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, const int *piv,
+                                                      BackOut o, Sel sel) {
+  constexpr int NT = 64 * NW, RPW = (RTM + NW - 1) / NW;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  if (o.skip && o.skip[leaf]) return;
+  const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
+  double *red = (double *)smem;                         // [NW]
+  double *xb = red + 8;                                 // [2][NCTM][256] published Y_k / X_k
+  T *D = (T *)(xb + 2 * NCTM * 256);                    // [RT][16][kDST]
+  int *pva = (int *)(D + (size_t)RT * 16 * kDST);       // [R] pivot rows in step order
+  const T *Ml = M + leaf_stride(g) * wi;
+  stage_inverse_diag<T, PASSES>(g, Ml, piv + (size_t)wi * R, D, pva, tid, NT);
 
   const int cl = lane & 15, rq = lane >> 4;
   // this wavefront's row tiles i = li*NW + wv, gathered in step order
@@ -1933,6 +1945,111 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
     if (k - 1 >= 0) {
       load_a(a0, k - 2);
       step(k - 1, false, a1);
+    }
+  }
+  if (o.mode == BACK_ACCUM) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
+    if (lane == 0) red[wv] = nd;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NW; ++w) sum += red[w];
+      o.norms[kNormStride * (size_t)leaf + 16] = sum;
+    }
+  }
+}
+
+// The refinement correction (forward then backward, FP32 factors) with each
+// wavefront owning one right-hand-side column tile instead: it keeps all RT
+// row tiles of that column tile in its accumulators and walks both
+// substitutions alone, so that after the shared prologue (pivots, inverted
+// diagonal blocks) no barrier is left; each wavefront reads the factor
+// tiles it needs itself (the wavefronts of a leaf share them through
+// L1/L2).  Measured faster than the row-owned kernel for this two-pass
+// launch (1.26 vs 1.57 ms at p = 16), whose per-step barriers then dominate.
+template <int RTM>
+__global__ void __launch_bounds__(320) k_solve_cols(Geom g, const float *M, const int *piv,
+                                                    BackOut o) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int NT = blockDim.x, NW = NT >> 6;
+  const int leaf = wi;
+  if (o.skip && o.skip[leaf]) return;
+  const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb;
+  double *red = (double *)smem;                          // [8]
+  float *D = (float *)(red + 8);                         // [RT][16][kDST]
+  int *pva = (int *)(D + (size_t)RT * 16 * kDST);        // [R]
+  const float *Ml = M + leaf_stride(g) * wi;
+  stage_inverse_diag<float, 3>(g, Ml, piv + (size_t)wi * R, D, pva, tid, NT);
+
+  const int cl = lane & 15, rq = lane >> 4, col = wv * 16 + cl;
+  d4 y[RTM];
+#pragma unroll
+  for (int k = 0; k < RTM; ++k) {
+    if (k < RT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        y[k][q] = (double)Ml[tix<float>(pva[16 * k + 4 * q + rq], R + col, CT)];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RTM; ++k) {
+    if (k < RT) {
+      const float *Db = D + k * 16 * kDST;
+      d4 nk = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int c = 4 * kc + rq;
+        const double a = cl > c ? (double)Db[cl * kDST + c] : (cl == c ? 1.0 : 0.0);
+        nk = mfma64(a, y[k][kc], nk);
+      }
+      y[k] = nk;
+#pragma unroll
+      for (int i = k + 1; i < RTM; ++i) {
+        if (i < RT) {
+          const int pr = pva[16 * i + cl];
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc)
+            y[i] = mfma64((double)Ml[tix<float>(pr, 16 * k + 4 * kc + rq, CT)], -nk[kc], y[i]);
+        }
+      }
+    }
+  }
+  double nd = 0.0;
+#pragma unroll
+  for (int k = RTM - 1; k >= 0; --k) {
+    if (k < RT) {
+      const float *Db = D + k * 16 * kDST;
+      d4 xk = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int c = 4 * kc + rq;
+        xk = mfma64(cl <= c ? (double)Db[cl * kDST + c] : 0.0, y[k][kc], xk);
+      }
+#pragma unroll
+      for (int i = 0; i < k; ++i) {
+        const int pr = pva[16 * i + cl];
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          y[i] = mfma64((double)Ml[tix<float>(pr, 16 * k + 4 * kc + rq, CT)], -xk[kc], y[i]);
+      }
+      if (col < g.nrhs) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ii = 16 * k + 4 * q + rq;
+          if (ii >= ni) continue;
+          const double v = xk[q];
+          double *dst = (col < nb) ? o.Xt + ((size_t)leaf * nb + col) * ni + ii
+                                   : o.h + (size_t)leaf * ni + ii;
+          if (o.mode == BACK_STORE) {
+            *dst = v;
+          } else {
+            *dst += v;
+            nd += v * v;
+          }
+        }
+      }
     }
   }
   if (o.mode == BACK_ACCUM) {
@@ -2778,11 +2895,32 @@ hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const 
   return launch_trisolve<double, 1>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
 }
 
+template <int RTM>
+hipError_t launch_solve_cols_t(const Geom &g, int nleaf, const float *M, const int *piv,
+                               const BackOut &o, hipStream_t s) {
+  if (g.RT > RTM) return hipErrorInvalidValue;
+  const size_t lds = sizeof(double) * 8 + sizeof(float) * (size_t)g.RT * 16 * kDST +
+                     sizeof(int) * (size_t)g.R;
+  hipError_t e = set_lds(k_solve_cols<RTM>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_solve_cols<RTM>), dim3(nleaf), dim3(64 * (g.CT - g.RT)), lds, s, g, M,
+                     piv, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_cols(const Geom &g, int nleaf, const float *M, const int *piv,
+                             const BackOut &o, hipStream_t s) {
+  if (g.RT <= 4) return launch_solve_cols_t<4>(g, nleaf, M, piv, o, s);
+  if (g.RT <= 8) return launch_solve_cols_t<8>(g, nleaf, M, piv, o, s);
+  if (g.RT <= 13) return launch_solve_cols_t<13>(g, nleaf, M, piv, o, s);
+  return launch_solve_cols_t<16>(g, nleaf, M, piv, o, s);
+}
+
 hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv,
                                const int *rstep, const BackOut &o, int nch, hipStream_t s) {
   if (solve_rr_applies(g)) {
     if (nch != 1) return hipErrorInvalidValue;
-    return launch_solve_rr<float, 3>(g, nleaf, (const float *)M, piv, o, s, Sel());
+    return launch_solve_cols(g, nleaf, (const float *)M, piv, o, s);
   }
   return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel(), nch);
 }
