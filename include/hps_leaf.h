@@ -94,6 +94,9 @@ typedef struct hps_batch hps_batch;
 /* Create a context bound to `stream` (a hipStream_t; NULL = default stream)
  * on the current device.  *out receives the handle. */
 hps_status hps_ctx_create(void *stream, hps_ctx **out);
+/* Release a context (NULL is a no-op).  Batches built on it must be
+ * destroyed first.  Everything is released even if a HIP call fails; the
+ * first failure is returned as HPS_ERR_HIP. */
 hps_status hps_ctx_destroy(hps_ctx *ctx);
 
 /* Set up a batch of leaf groups: validates the descriptors, builds the

@@ -250,13 +250,18 @@ hps_status hps_ctx_create(void *stream, hps_ctx **out) {
 
 hps_status hps_ctx_destroy(hps_ctx *ctx) {
   if (!ctx) return HPS_OK;
+  // release everything, report the first failure
+  hipError_t first = hipSuccess;
+  auto keep = [&](hipError_t e) {
+    if (first == hipSuccess) first = e;
+  };
   for (auto &r : ctx->recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    keep(hipEventDestroy(r.a));
+    keep(hipEventDestroy(r.b));
   }
-  for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  for (hipEvent_t e : ctx->pool) keep(hipEventDestroy(e));
   delete ctx;
-  return HPS_OK;
+  return from_hip(first);
 }
 
 hps_status hps_ctx_set_timing(hps_ctx *ctx, int enable) {
@@ -344,7 +349,7 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
     }
     if (hipMemcpy(G.dtab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) !=
         hipSuccess) {
-      hipFree(G.dtab);
+      (void)hipFree(G.dtab);   // the copy's failure is the error reported
       st = HPS_ERR_HIP;
       break;
     }
