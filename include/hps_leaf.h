@@ -214,8 +214,12 @@ hps_status hps_batch_stats(const hps_batch *b, int *refine_steps, int *fp64_redo
 hps_status hps_ctx_set_timing(hps_ctx *ctx, int enable);
 hps_status hps_ctx_phase_times(hps_ctx *ctx, double *ms, int *launches);
 
+/* Free a batch and its device buffers (NULL is a no-op).  hipFree
+ * synchronises the device, so work still queued on the batch completes
+ * first.  Every buffer is released even if one free fails (HPS_ERR_HIP). */
 hps_status hps_batch_destroy(hps_batch *b);
 
+/* Static text naming a status code. */
 const char *hps_status_string(hps_status s);
 
 #ifdef __cplusplus
