@@ -2180,124 +2180,134 @@ __global__ void __launch_bounds__(NT) k_residual(Geom g, float *M32, const doubl
   }
 }
 
-// The same residual for leaves with at most 16 interior nodes per line
-// (p <= 18).  Each thread forms its row's 2m line weights once per leaf, in
-// registers (lines padded to 16 nodes with zero weights), and every staged
-// column is laid out twice in LDS, by x1-lines and by x2-lines (18-double
-// row stride, so that the lines of a wavefront's rows fall on different
-// banks), so that both line sums of a row read contiguous 128-bit words.
-template <int CW>
-__global__ void __launch_bounds__(256) k_residual_l(Geom g, float *M32, const double *Xt,
+// The same residual on the MFMA units for leaves with at most 16 interior
+// nodes per line (p <= 18).  For one column of [X h], with G the m x m grid
+// of its values (G[i][j] at interior node (i, j), zero-padded to 16 x 16),
+// both line sums of every row are tile products with the interior block of
+// a differentiation matrix D (D1 or D2):
+//   along x1: sum_k D[i][k] G[k][j] = (D G)[i][j]
+//   along x2: sum_k D[j][k] G[i][k] = (G D^T)[i][j]
+// and each node's own coefficients combine the four products.  Wavefront w
+// takes every fourth column and stages its grid in a private LDS tile; the
+// MFMA accumulator layout puts node (4q + lane/16, lane%16) in register q of
+// a lane, which is also where the lane's B operand of D G holds G.
+__global__ void __launch_bounds__(256) k_residual_m(Geom g, float *M32, const double *Xt,
                                                     const double *h, const double *f,
                                                     const int *skip, double *norms) {
-  constexpr int NT = 256, LS = 18;
-  __shared__ __align__(16) double xl[CW][16 * LS];   // [c][j-1][k-1] = x(k, j): x1-lines
-  __shared__ __align__(16) double yl[CW][16 * LS];   // [c][i-1][k-1] = x(i, k): x2-lines
-  __shared__ double red[NT / 64][2];
-  __shared__ double sD[18 * 18], sD2[18 * 18];
+  constexpr int NW = 4, GS = 17;
+  __shared__ double gs[NW][16 * GS];
+  __shared__ double red[NW][2];
   const int leaf = blockIdx.x;
   if (skip && skip[leaf]) return;
-  stage_tables(g, sD, sD2);
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, cl = lane & 15, rq = lane >> 4;
   const LeafScale sc = leaf_scale(g, leaf);
   const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R, CT = g.CT;
   float *Ml = M32 + leaf_stride(g) * leaf;
   const int ncol = (h && f) ? nb + 1 : nb;
-  const int r = threadIdx.x;   // this thread's row
-  int i = 1, j = 1;
-  double kb = 0.0, bw0 = 0.0, bw1 = 0.0, bs0 = 0.0, bs1 = 0.0;
-  double wx[16], wy[16];
+  // A operand of D G (and B operand of G D^T): D[cl + 1][4kc + rq + 1]
+  double d1[4], d2[4];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) wx[k] = wy[k] = 0.0;
-  if (r < ni) {
-    i = r % m + 1;
-    j = r / m + 1;
-    const size_t n = (size_t)leaf * p * p + i + (size_t)p * j;
-    const double ax2 = (g.a11 ? g.a11[n] : 1.0) * sc.sx * sc.sx;
-    const double ax1 = (g.c1 ? g.c1[n] : 0.0) * sc.sx;
-    const double ay2 = (g.a22 ? g.a22[n] : 1.0) * sc.sy * sc.sy;
-    const double ay1 = (g.c2 ? g.c2[n] : 0.0) * sc.sy;
-    kb = g.k2b ? g.k2b[n] : 0.0;
+  for (int kc = 0; kc < 4; ++kc) {
+    const int k = 4 * kc + rq;
+    const bool in = cl < m && k < m;
+    d1[kc] = in ? g.D[(cl + 1) * p + k + 1] : 0.0;
+    d2[kc] = in ? g.D2[(cl + 1) * p + k + 1] : 0.0;
+  }
+  // coefficients of this lane's nodes (i, j) = (4q + rq, cl)
+  double ax2[4], ax1[4], ay2[4], ay1[4], kb[4], bw0[4], bw1[4], bs0[4], bs1[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      if (k < m) {
-        wx[k] = ax2 * sD2[i * p + k + 1] + ax1 * sD[i * p + k + 1];
-        wy[k] = ay2 * sD2[j * p + k + 1] + ay1 * sD[j * p + k + 1];
-      }
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * q + rq, j = cl;
+    ax2[q] = ax1[q] = ay2[q] = ay1[q] = kb[q] = bw0[q] = bw1[q] = bs0[q] = bs1[q] = 0.0;
+    if (i < m && j < m) {
+      const size_t n = (size_t)leaf * p * p + (i + 1) + (size_t)p * (j + 1);
+      ax2[q] = (g.a11 ? g.a11[n] : 1.0) * sc.sx * sc.sx;
+      ax1[q] = (g.c1 ? g.c1[n] : 0.0) * sc.sx;
+      ay2[q] = (g.a22 ? g.a22[n] : 1.0) * sc.sy * sc.sy;
+      ay1[q] = (g.c2 ? g.c2[n] : 0.0) * sc.sy;
+      kb[q] = g.k2b ? g.k2b[n] : 0.0;
+      bw0[q] = -(ax2[q] * g.D2[(i + 1) * p] + ax1[q] * g.D[(i + 1) * p]);
+      bw1[q] = -(ax2[q] * g.D2[(i + 1) * p + p - 1] + ax1[q] * g.D[(i + 1) * p + p - 1]);
+      bs0[q] = -(ay2[q] * g.D2[(j + 1) * p] + ay1[q] * g.D[(j + 1) * p]);
+      bs1[q] = -(ay2[q] * g.D2[(j + 1) * p + p - 1] + ay1[q] * g.D[(j + 1) * p + p - 1]);
     }
-    bw0 = -(ax2 * sD2[i * p] + ax1 * sD[i * p]);
-    bw1 = -(ax2 * sD2[i * p + p - 1] + ax1 * sD[i * p + p - 1]);
-    bs0 = -(ay2 * sD2[j * p] + ay1 * sD[j * p]);
-    bs1 = -(ay2 * sD2[j * p + p - 1] + ay1 * sD[j * p + p - 1]);
   }
-  // the padding of the lines is never written by the staging below
-  for (int e = threadIdx.x; e < CW * 16 * LS; e += NT) {
-    (&xl[0][0])[e] = 0.0;
-    (&yl[0][0])[e] = 0.0;
+  // grid positions of the column entries e = lane + 64 t this lane stages
+  int gpos[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = lane + 64 * t;
+    gpos[t] = e < ni ? (e % m) * GS + e / m : -1;
   }
+  double *G = gs[wv];
+  for (int e = lane; e < 16 * GS; e += 64) G[e] = 0.0;   // padding stays zero
   double nr = 0.0, nx = 0.0;
-  const int ngrp = (ncol + CW - 1) / CW;
-  const int g0 = (ngrp * (int)blockIdx.y) / (int)gridDim.y;
-  const int g1 = (ngrp * ((int)blockIdx.y + 1)) / (int)gridDim.y;
-  for (int c0 = g0 * CW; c0 < min(g1 * CW, ncol); c0 += CW) {
-    const int cw = min(CW, ncol - c0);
-    __syncthreads();
-    // each thread stages its own row of the chunk's columns (coalesced)
-    if (r < ni) {
+  const int c0 = (ncol * (int)blockIdx.y) / (int)gridDim.y;
+  const int c1 = (ncol * ((int)blockIdx.y + 1)) / (int)gridDim.y;
+  // the next columns' values are loaded while the current one is processed
+  auto load_col = [&](int c, double (&v)[4]) {
+    const double *src = c < nb ? Xt + ((size_t)leaf * nb + c) * ni : h + (size_t)leaf * ni;
 #pragma unroll
-      for (int c = 0; c < CW; ++c) {
-        if (c >= cw) continue;
-        const int col = c0 + c;
-        const double v = (col < nb) ? Xt[((size_t)leaf * nb + col) * ni + r] : h[(size_t)leaf * ni + r];
-        xl[c][(j - 1) * LS + i - 1] = v;
-        yl[c][(i - 1) * LS + j - 1] = v;
-      }
-    }
-    __syncthreads();
-    if (r >= ni) {
-      if (r < R)
-        for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = 0.0f;
-      continue;
-    }
-    float out[CW];
+    for (int t = 0; t < 4; ++t) v[t] = gpos[t] >= 0 ? src[lane + 64 * t] : 0.0;
+  };
+  // (PD columns ahead; four measured no faster than two)
+  constexpr int PD = 2;
+  double nxt[PD][4];
 #pragma unroll
-    for (int c = 0; c < CW; ++c) {
-      out[c] = 0.0f;
-      if (c >= cw) continue;
-      const double *xr = &xl[c][(j - 1) * LS];
-      const double *yr = &yl[c][(i - 1) * LS];
-      const double x = xr[i - 1];
+  for (int d = 0; d < PD; ++d) {
+    const int cd = c0 + wv + d * NW;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) nxt[d][t] = 0.0;
+    if (cd < c1) load_col(cd, nxt[d]);
+  }
+  for (int c = c0 + wv; c < c1; c += NW) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (gpos[t] >= 0) G[gpos[t]] = nxt[0][t];
+#pragma unroll
+    for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) nxt[d][t] = nxt[d + 1][t];
+    wave_lds_fence<double>();
+    if (c + PD * NW < c1) load_col(c + PD * NW, nxt[PD - 1]);
+    double bo[4], ao[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      bo[kc] = G[(4 * kc + rq) * GS + cl];
+      ao[kc] = G[cl * GS + 4 * kc + rq];
+    }
+    d4 t1x = {0.0, 0.0, 0.0, 0.0}, t2x = t1x, t1y = t1x, t2y = t1x;
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      t1x = mfma64(d1[kc], bo[kc], t1x);
+      t2x = mfma64(d2[kc], bo[kc], t2x);
+      t1y = mfma64(ao[kc], d1[kc], t1y);
+      t2y = mfma64(ao[kc], d2[kc], t2y);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 4 * q + rq, j = cl;
+      if (i >= m || j >= m) continue;
+      const int r = i + m * j;
+      const double x = bo[q];
       // -(A_ii x) = k2b x + sum over both lines of (a d2 + c d1) x
-      double acc = kb * x;
-#pragma unroll
-      for (int k = 0; k < 16; k += 2) {
-        const double2 a = *(const double2 *)(xr + k);
-        const double2 b = *(const double2 *)(yr + k);
-        acc += wx[k] * a.x + wx[k + 1] * a.y + wy[k] * b.x + wy[k + 1] * b.y;
-      }
-      const int col = c0 + c;
+      const double acc = kb[q] * x + ax2[q] * t2x[q] + ax1[q] * t1x[q] + ay2[q] * t2y[q] +
+                         ay1[q] * t1y[q];
       double bval = 0.0;   // entry of [A_ib f] in this row
-      if (col == nb) bval = f[(size_t)leaf * ni + r];
-      else if (col == j - 1) bval = bw0;
-      else if (col == m + j - 1) bval = bw1;
-      else if (col == 2 * m + i - 1) bval = bs0;
-      else if (col == 3 * m + i - 1) bval = bs1;
+      if (c == nb) bval = f[(size_t)leaf * ni + r];
+      else if (c == j) bval = bw0[q];
+      else if (c == m + j) bval = bw1[q];
+      else if (c == 2 * m + i) bval = bs0[q];
+      else if (c == 3 * m + i) bval = bs1[q];
       const double res = bval + acc;
       nr += res * res;
       nx += x * x;
-      out[c] = (float)res;
+      Ml[tix<float>(r, R + c, CT)] = (float)res;
     }
-    // the chunk's CW columns of this row are contiguous in its work-matrix
-    // tile (chunks start at multiples of CW, CW divides 16)
-    if (cw == CW) {
-      float4 *dst = (float4 *)(Ml + tix<float>(r, R + c0, CT));
-#pragma unroll
-      for (int q = 0; q < CW / 4; ++q) dst[q] = make_float4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
-    } else {
-      for (int c = 0; c < cw; ++c) Ml[tix<float>(r, R + c0 + c, CT)] = out[c];
-    }
+    for (int r = ni + lane; r < R; r += 64) Ml[tix<float>(r, R + c, CT)] = 0.0f;
+    // the next column's staging must not overtake this column's reads
+    wave_lds_fence<double>();
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     nr += __shfl_xor(nr, off);
@@ -2310,7 +2320,7 @@ __global__ void __launch_bounds__(256) k_residual_l(Geom g, float *M32, const do
   __syncthreads();
   if (threadIdx.x < 2) {
     double a = 0.0;
-    for (int w = 0; w < NT / 64; ++w) a += red[w][threadIdx.x];
+    for (int w = 0; w < NW; ++w) a += red[w][threadIdx.x];
     norms[kNormStride * (size_t)leaf + 8 + 4 * threadIdx.x + blockIdx.y] = a;
   }
 }
@@ -2814,8 +2824,8 @@ hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *X
                            int nch, hipStream_t s) {
   if (g.m <= 16 && g.R <= 256) {
     if (nch < 1 || nch > kMaxChunks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_residual_l<4>), dim3(nleaf, nch), dim3(256), 0, s, g, M32, Xt, h, f,
-                       skip, norms);
+    hipLaunchKernelGGL(k_residual_m, dim3(nleaf, nch), dim3(256), 0, s, g, M32, Xt, h, f, skip,
+                       norms);
     return hipGetLastError();
   }
   if (g.R <= 256) return launch_residual_t<256, 8>(g, nleaf, M32, Xt, h, f, skip, norms, nch, s);

@@ -361,6 +361,21 @@ def test_refinement_stats_typical_leaves(torch):
     B.close()
 
 
+@pytest.mark.parametrize("p", [6, 8, 12, 16, 18])
+def test_refinement_converges_without_redo_small_orders(torch, p):
+    """The residual kernels of the orders up to 18 (interior lines of at most
+    16 nodes) drive the refinement to the default target on well-conditioned
+    leaves: a wrong residual would show as leaves handed to the FP64 redo
+    (which would still return correct results)."""
+    _say(f"refinement without redo p={p}")
+    prob = _small(p, 3)
+    B = _batch([prob])
+    S, w, info, st = B.condense(prec=hps.HPS_FP32_REFINE, max_refine=2, sync=True)
+    assert st == hps.HPS_OK
+    assert hps.hps_batch_stats(B.batch) == (2, 0)
+    B.close()
+
+
 def test_fixed_step_count_without_stop_test(torch):
     """tol >= 1 applies exactly max_refine corrections with no test and no
     FP64 redo: the error in X falls with every step (the contraction of
