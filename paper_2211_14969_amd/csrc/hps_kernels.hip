@@ -2325,6 +2325,132 @@ __global__ void __launch_bounds__(256) k_residual_m(Geom g, float *M32, const do
   }
 }
 
+// The MFMA residual for 24 <= m <= 30 (p = 26 ... 32): the grid of a column is
+// 2 x 2 tiles, each output tile (I, J) takes the products
+//   (D G)(I, J) = sum_K D(I, K) G(K, J),  (G D^T)(I, J) = sum_K G(I, K) D(J, K)^T
+// for D1 and D2 (32 tile products per output tile); D's tiles stay in
+// registers (their A-operand layout is also the B-operand layout of D^T),
+// the nodes' coefficients are read per output tile, and the boundary
+// couplings are formed only at the nodes that have one.  A column's values
+// are loaded one column ahead.
+__global__ void __launch_bounds__(256) k_residual_m2(Geom g, float *M32, const double *Xt,
+                                                     const double *h, const double *f,
+                                                     const int *skip, double *norms) {
+  constexpr int NW = 4, GS = 33, NV = 15;   // NV * 64 >= 32 * 32 > ni
+  __shared__ double gs[NW][32 * GS];
+  __shared__ double red[NW][2];
+  const int leaf = blockIdx.x;
+  if (skip && skip[leaf]) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, cl = lane & 15, rq = lane >> 4;
+  const LeafScale sc = leaf_scale(g, leaf);
+  const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R, CT = g.CT;
+  float *Ml = M32 + leaf_stride(g) * leaf;
+  const int ncol = (h && f) ? nb + 1 : nb;
+  // dd[0/1][I][K][kc] = D1/D2[16I + cl + 1][16K + 4kc + rq + 1] (zero outside the interior)
+  double dd[2][2][2][4];
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int K = 0; K < 2; ++K)
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) {
+        const int i = 16 * I + cl, k = 16 * K + 4 * kc + rq;
+        const bool in = i < m && k < m;
+        dd[0][I][K][kc] = in ? g.D[(i + 1) * p + k + 1] : 0.0;
+        dd[1][I][K][kc] = in ? g.D2[(i + 1) * p + k + 1] : 0.0;
+      }
+  int gpos[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const int e = lane + 64 * t;
+    gpos[t] = e < ni ? (e % m) * GS + e / m : -1;
+  }
+  double *G = gs[wv];
+  for (int e = lane; e < 32 * GS; e += 64) G[e] = 0.0;   // padding stays zero
+  auto load_col = [&](int c, double (&v)[NV]) {
+    const double *src = c < nb ? Xt + ((size_t)leaf * nb + c) * ni : h + (size_t)leaf * ni;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = gpos[t] >= 0 ? src[lane + 64 * t] : 0.0;
+  };
+  double nr = 0.0, nx = 0.0;
+  const int c0 = (ncol * (int)blockIdx.y) / (int)gridDim.y;
+  const int c1 = (ncol * ((int)blockIdx.y + 1)) / (int)gridDim.y;
+  double nxt[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) nxt[t] = 0.0;
+  if (c0 + wv < c1) load_col(c0 + wv, nxt);
+  for (int c = c0 + wv; c < c1; c += NW) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t)
+      if (gpos[t] >= 0) G[gpos[t]] = nxt[t];
+    wave_lds_fence<double>();
+    if (c + NW < c1) load_col(c + NW, nxt);
+#pragma unroll
+    for (int I = 0; I < 2; ++I) {
+#pragma unroll
+      for (int J = 0; J < 2; ++J) {
+        if (16 * I >= m || 16 * J >= m) continue;
+        d4 t1x = {0.0, 0.0, 0.0, 0.0}, t2x = t1x, t1y = t1x, t2y = t1x;
+#pragma unroll
+        for (int K = 0; K < 2; ++K) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            const double bo = G[(16 * K + 4 * kc + rq) * GS + 16 * J + cl];   // G(K, J)
+            const double ao = G[(16 * I + cl) * GS + 16 * K + 4 * kc + rq];   // G(I, K)
+            t1x = mfma64(dd[0][I][K][kc], bo, t1x);
+            t2x = mfma64(dd[1][I][K][kc], bo, t2x);
+            t1y = mfma64(ao, dd[0][J][K][kc], t1y);
+            t2y = mfma64(ao, dd[1][J][K][kc], t2y);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = 16 * I + 4 * q + rq, j = 16 * J + cl;
+          if (i >= m || j >= m) continue;
+          const int r = i + m * j;
+          const size_t n = (size_t)leaf * p * p + (i + 1) + (size_t)p * (j + 1);
+          const double ax2 = (g.a11 ? g.a11[n] : 1.0) * sc.sx * sc.sx;
+          const double ax1 = (g.c1 ? g.c1[n] : 0.0) * sc.sx;
+          const double ay2 = (g.a22 ? g.a22[n] : 1.0) * sc.sy * sc.sy;
+          const double ay1 = (g.c2 ? g.c2[n] : 0.0) * sc.sy;
+          const double kb = g.k2b ? g.k2b[n] : 0.0;
+          const double x = G[i * GS + j];
+          // -(A_ii x) = k2b x + sum over both lines of (a d2 + c d1) x
+          const double acc = kb * x + ax2 * t2x[q] + ax1 * t1x[q] + ay2 * t2y[q] + ay1 * t1y[q];
+          double bval = 0.0;   // entry of [A_ib f] in this row
+          if (c == nb) bval = f[(size_t)leaf * ni + r];
+          else if (c == j) bval = -(ax2 * g.D2[(i + 1) * p] + ax1 * g.D[(i + 1) * p]);
+          else if (c == m + j) bval = -(ax2 * g.D2[(i + 1) * p + p - 1] + ax1 * g.D[(i + 1) * p + p - 1]);
+          else if (c == 2 * m + i) bval = -(ay2 * g.D2[(j + 1) * p] + ay1 * g.D[(j + 1) * p]);
+          else if (c == 3 * m + i) bval = -(ay2 * g.D2[(j + 1) * p + p - 1] + ay1 * g.D[(j + 1) * p + p - 1]);
+          const double res = bval + acc;
+          nr += res * res;
+          nx += x * x;
+          Ml[tix<float>(r, R + c, CT)] = (float)res;
+        }
+      }
+    }
+    for (int r = ni + lane; r < R; r += 64) Ml[tix<float>(r, R + c, CT)] = 0.0f;
+    // the next column's staging must not overtake this column's reads
+    wave_lds_fence<double>();
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    nr += __shfl_xor(nr, off);
+    nx += __shfl_xor(nx, off);
+  }
+  if (lane == 0) {
+    red[wv][0] = nr;
+    red[wv][1] = nx;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double a = 0.0;
+    for (int w = 0; w < NW; ++w) a += red[w][threadIdx.x];
+    norms[kNormStride * (size_t)leaf + 8 + 4 * threadIdx.x + blockIdx.y] = a;
+  }
+}
+
 // Stop test of the refinement, per leaf, after the residual r_k of X_k: the
 // estimated forward error rho ||dX_k|| is at most tol ||X_k||, where dX_k is
 // the last correction and rho, the contraction factor of the iteration, is
@@ -2825,6 +2951,15 @@ hipError_t launch_residual(const Geom &g, int nleaf, float *M32, const double *X
   if (g.m <= 16 && g.R <= 256) {
     if (nch < 1 || nch > kMaxChunks) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_residual_m, dim3(nleaf, nch), dim3(256), 0, s, g, M32, Xt, h, f, skip,
+                       norms);
+    return hipGetLastError();
+  }
+  // 2 x 2 tiles per grid: worth their padding from 24 nodes per line on
+  // (measured 0.74x the thread-per-row kernel's speed at m = 18, 1.7x at
+  // m = 30); a column must fit the 15 values per lane it stages
+  if (g.m >= 24 && g.m <= 32 && g.ni <= 64 * 15) {
+    if (nch < 1 || nch > kMaxChunks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_residual_m2, dim3(nleaf, nch), dim3(256), 0, s, g, M32, Xt, h, f, skip,
                        norms);
     return hipGetLastError();
   }
