@@ -218,8 +218,11 @@ def _forced_problem(p, nx=2, ny=2):
                           g=u, exact=u, f=f)
 
 
-@pytest.mark.parametrize("prec,p", [(hps.HPS_FP64, 10), (hps.HPS_FP64, 17),
-                                    (hps.HPS_FP32_REFINE, 10), (hps.HPS_FP32_REFINE, 17)])
+# p = 18 with f: five right-hand-side column tiles (the widest register-
+# resident solves); p = 28 with f: the 2 x 2-tile MFMA residual's f column.
+@pytest.mark.parametrize("prec,p", [(hps.HPS_FP64, 10), (hps.HPS_FP64, 17), (hps.HPS_FP64, 18),
+                                    (hps.HPS_FP32_REFINE, 10), (hps.HPS_FP32_REFINE, 17),
+                                    (hps.HPS_FP32_REFINE, 18), (hps.HPS_FP32_REFINE, 28)])
 def test_condense_with_body_load(torch, prec, p):
     _say(f"forced prec={prec} p={p}")
     prob = _forced_problem(p)
