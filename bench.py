@@ -34,15 +34,15 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # 1.0 against a 1 GiB device copy), keyed by the sha256 prefix of the kernel
 # source it was measured on, the workload and the precision.
 MEASURED_TRAFFIC = {
-    ("ff7518ea4bf12915", "bump_64x64_p16", "fp64"): {
+    ("24409b08b3431586", "bump_64x64_p16", "fp64"): {
         "kernel": "k_factor2_t<double, 2>",
-        "fetch_bytes": 3005532.125 * 2.0 * 1024, "write_bytes": 8168581.385 * 1.0 * 1024},
-    ("ff7518ea4bf12915", "bump_64x64_p16", "fp32"): {
+        "fetch_bytes": 3003605.458 * 2.0 * 1024, "write_bytes": 8168552.833 * 1.0 * 1024},
+    ("24409b08b3431586", "bump_64x64_p16", "fp32"): {
         "kernel": "k_factor2_t<float, 3>",
-        "fetch_bytes": 1477264.479 * 2.0 * 1024, "write_bytes": 4122085.208 * 1.0 * 1024},
-    ("ff7518ea4bf12915", "bumps_32x32_p32", "fp64"): {
+        "fetch_bytes": 1477221.146 * 2.0 * 1024, "write_bytes": 4122015.198 * 1.0 * 1024},
+    ("24409b08b3431586", "bumps_32x32_p32", "fp64"): {
         "kernel": "k_factorP<double, 512, 2>",
-        "fetch_bytes": 51460195.229 * 2.0 * 1024, "write_bytes": 93055321.542 * 1.0 * 1024},
+        "fetch_bytes": 51476974.354 * 2.0 * 1024, "write_bytes": 93059252.844 * 1.0 * 1024},
 }
 
 

@@ -1714,24 +1714,22 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
 }
 
 // ---------------------------------------------------------------------------
-// Triangular solves for work matrices of at most 256 rows with the
+// Back substitution for work matrices of at most 256 rows with the
 // right-hand sides held in registers.  Row tile i of the right-hand sides
 // (all its column tiles, in pivot (step) order) lives in the FP64 MFMA
 // accumulators of wavefront i mod NW for the whole solve.  The 16 x 16
 // diagonal blocks of the factors are inverted once per leaf into LDS (one
 // column per thread), so every step of the block substitution is a tile
 // product:
-//   forward   Y_k = L_kk^{-1} (R_k - sum_{j<k} L_kj Y_j)
-//   backward  X_k = U_kk^{-1} (Y_k - sum_{j>k} U_kj X_j)
-// where L_kj / U_kj is tile j of the 16 pivot rows of panel k.  Step k: the
-// owner of row tile k forms Y_k / X_k and publishes it in LDS; after one
-// barrier every wavefront applies it to its own row tiles.  Each factor tile
-// is thus read once per leaf (by the wavefront owning its row tile) and used
-// for every column tile, and the tiles of step k-1 are loaded while step k
-// runs.  The right-hand sides are read once and the solution written once.
-// PASSES: 1 backward only, 3 forward then backward.  RTM bounds RT and NCTM
-// the number of right-hand-side column tiles (register arrays are indexed
-// statically).
+//   X_k = U_kk^{-1} (Y_k - sum_{j>k} U_kj X_j)
+// where U_kj is tile j of the 16 pivot rows of panel k.  Step k: the owner
+// of row tile k forms X_k and publishes it in LDS; after one barrier every
+// wavefront applies it to its own row tiles.  Each factor tile is thus read
+// once per leaf (by the wavefront owning its row tile) and used for every
+// column tile, and the tiles of step k-1 are loaded while step k runs.  The
+// right-hand sides are read once and the solution written once.  RTM bounds
+// RT and NCTM the number of right-hand-side column tiles (register arrays
+// are indexed statically).
 // ---------------------------------------------------------------------------
 constexpr int kDST = 17;   // LDS row stride of the diagonal blocks
 
@@ -1806,7 +1804,7 @@ __device__ __forceinline__ void stage_inverse_diag(const Geom &g, const T *Ml, c
 
 }
 
-template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
+template <typename T, int RTM, int NCTM, int NW, int MINW>
 __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, const int *piv,
                                                       BackOut o, Sel sel) {
   constexpr int NT = 64 * NW, RPW = (RTM + NW - 1) / NW;
@@ -1817,11 +1815,11 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
   if (o.skip && o.skip[leaf]) return;
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
   double *red = (double *)smem;                         // [NW]
-  double *xb = red + 8;                                 // [2][NCTM][256] published Y_k / X_k
+  double *xb = red + 8;                                 // [2][NCTM][256] published X_k
   T *D = (T *)(xb + 2 * NCTM * 256);                    // [RT][16][kDST]
   int *pva = (int *)(D + (size_t)RT * 16 * kDST);       // [R] pivot rows in step order
   const T *Ml = M + leaf_stride(g) * wi;
-  stage_inverse_diag<T, PASSES>(g, Ml, piv + (size_t)wi * R, D, pva, tid, NT);
+  stage_inverse_diag<T, 1>(g, Ml, piv + (size_t)wi * R, D, pva, tid, NT);
 
   const int cl = lane & 15, rq = lane >> 4;
   // this wavefront's row tiles i = li*NW + wv, gathered in step order
@@ -1852,8 +1850,8 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
   };
   double nd = 0.0;
   // the owner of row tile k applies the inverted diagonal block to it,
-  // publishes the result in LDS and (backward) writes it out
-  auto form = [&](int k, bool fwd) __attribute__((always_inline)) {
+  // publishes the result in LDS and writes it out
+  auto form = [&](int k) __attribute__((always_inline)) {
     const T *Db = D + k * 16 * kDST;
     double *xk = xb + (k & 1) * NCTM * 256;
 #pragma unroll
@@ -1867,14 +1865,13 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
         for (int kc = 0; kc < 4; ++kc) {
           const int cc = 4 * kc + rq;
           const double dv = (double)Db[cl * kDST + cc];
-          const double av = fwd ? (cl > cc ? dv : (cl == cc ? 1.0 : 0.0)) : (cl <= cc ? dv : 0.0);
-          z = mfma64(av, y[li][c][kc], z);
+          z = mfma64(cl <= cc ? dv : 0.0, y[li][c][kc], z);
         }
         y[li][c] = z;
 #pragma unroll
         for (int q = 0; q < 4; ++q) xk[(c * 4 + q) * 64 + lane] = z[q];
         const int col = 16 * c + cl;
-        if (fwd || col >= g.nrhs) continue;
+        if (col >= g.nrhs) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int ii = 16 * k + 4 * q + rq;
@@ -1896,16 +1893,16 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
       }
     }
   };
-  // step k: everyone applies the published Y_k / X_k to their own row tiles
-  // (with the operands loaded one step earlier); the owner of the next row
-  // tile, whose last update this was, forms and publishes it before the
-  // barrier, so that forming is off the other wavefronts' path
-  auto step = [&](int k, bool fwd, const T (&a)[RPW][4]) __attribute__((always_inline)) {
+  // step k: everyone applies the published X_k to their own row tiles (with
+  // the operands loaded one step earlier); the owner of the next row tile,
+  // whose last update this was, forms and publishes it before the barrier,
+  // so that forming is off the other wavefronts' path
+  auto step = [&](int k, const T (&a)[RPW][4]) __attribute__((always_inline)) {
     const double *xk = xb + (k & 1) * NCTM * 256;
 #pragma unroll
     for (int li = 0; li < RPW; ++li) {
       const int i = li * NW + wv;
-      if (i >= RT || (fwd ? i <= k : i >= k)) continue;
+      if (i >= k) continue;
 #pragma unroll
       for (int c = 0; c < NCTM; ++c) {
         if (c >= NCT) continue;
@@ -1914,37 +1911,22 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
           y[li][c] = mfma64((double)a[li][kc], -xk[(c * 4 + kc) * 64 + lane], y[li][c]);
       }
     }
-    const int kn = fwd ? k + 1 : k - 1;
-    if (kn >= 0 && kn < RT) form(kn, fwd);
+    if (k >= 1) form(k - 1);
     lds_barrier();
   };
   T a0[RPW][4], a1[RPW][4];
-  if (PASSES & 2) {
-    load_a(a0, 0);
-    form(0, true);
-    lds_barrier();
-#pragma unroll 1
-    for (int k = 0; k < RT; k += 2) {
-      load_a(a1, k + 1);
-      step(k, true, a0);
-      if (k + 1 < RT) {
-        load_a(a0, k + 2);
-        step(k + 1, true, a1);
-      }
-    }
-  }
   // backward; X_k is written out by its owner when formed
   load_a(a0, RT - 1);
-  form(RT - 1, false);
+  form(RT - 1);
   lds_barrier();
 #pragma unroll 1
   for (int kk = 0; kk < RT; kk += 2) {
     const int k = RT - 1 - kk;
     load_a(a1, k - 1);
-    step(k, false, a0);
+    step(k, a0);
     if (k - 1 >= 0) {
       load_a(a0, k - 2);
-      step(k - 1, false, a1);
+      step(k - 1, a1);
     }
   }
   if (o.mode == BACK_ACCUM) {
@@ -2998,43 +2980,43 @@ bool solve_rr_applies(const Geom &g) {
   return solve_rr_enabled() && g.R <= 256 && nct >= 1 && nct <= 5;
 }
 
-template <typename T, int RTM, int NCTM, int NW, int MINW, int PASSES>
+template <typename T, int RTM, int NCTM, int NW, int MINW>
 hipError_t launch_solve_rr_t(const Geom &g, int nleaf, const T *M, const int *piv,
                              const BackOut &o, hipStream_t s, const Sel &sel) {
   if (g.RT > RTM || g.CT - g.RT > NCTM) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * (8 + 2 * NCTM * 256) +
                      sizeof(T) * (size_t)g.RT * 16 * kDST + sizeof(int) * (size_t)g.R;
-  hipError_t e = set_lds(k_solve_rr<T, RTM, NCTM, NW, MINW, PASSES>, lds);
+  hipError_t e = set_lds(k_solve_rr<T, RTM, NCTM, NW, MINW>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_solve_rr<T, RTM, NCTM, NW, MINW, PASSES>), dim3(nleaf), dim3(64 * NW), lds,
+  hipLaunchKernelGGL((k_solve_rr<T, RTM, NCTM, NW, MINW>), dim3(nleaf), dim3(64 * NW), lds,
                      s, g, M, piv, o, sel);
   return hipGetLastError();
 }
 
 // Up to 8 row tiles: four wavefronts, four per SIMD.  More: the FP64
 // back substitution keeps four wavefronts (four row tiles each, up to 232
-// registers, two wavefronts per SIMD), the FP32 solves take eight (at most
+// registers, two wavefronts per SIMD), the FP32 one takes eight (at most
 // 128 registers, four per SIMD); measured at p = 16 and 18.
-template <typename T, int PASSES>
+template <typename T>
 hipError_t launch_solve_rr(const Geom &g, int nleaf, const T *M, const int *piv, const BackOut &o,
                            hipStream_t s, const Sel &sel) {
   if (!solve_rr_applies(g)) return hipErrorNotSupported;
-  constexpr bool wide = !(std::is_same<T, double>::value && PASSES == 1);
+  constexpr bool wide = !std::is_same<T, double>::value;
   constexpr int NW = wide ? 8 : 4, MW = wide ? 4 : 2;
   const int nct = g.CT - g.RT;
   if (g.RT <= 4 && nct <= 4)
-    return launch_solve_rr_t<T, 4, 4, 4, 4, PASSES>(g, nleaf, M, piv, o, s, sel);
+    return launch_solve_rr_t<T, 4, 4, 4, 4>(g, nleaf, M, piv, o, s, sel);
   if (g.RT <= 8 && nct <= 4)
-    return launch_solve_rr_t<T, 8, 4, 4, 4, PASSES>(g, nleaf, M, piv, o, s, sel);
-  if (nct <= 4) return launch_solve_rr_t<T, 16, 4, NW, MW, PASSES>(g, nleaf, M, piv, o, s, sel);
-  return launch_solve_rr_t<T, 16, 5, NW, MW, PASSES>(g, nleaf, M, piv, o, s, sel);
+    return launch_solve_rr_t<T, 8, 4, 4, 4>(g, nleaf, M, piv, o, s, sel);
+  if (nct <= 4) return launch_solve_rr_t<T, 16, 4, NW, MW>(g, nleaf, M, piv, o, s, sel);
+  return launch_solve_rr_t<T, 16, 5, NW, MW>(g, nleaf, M, piv, o, s, sel);
 }
 
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
   if (solve_rr_applies(g)) {
-    if (fp32) return launch_solve_rr<float, 1>(g, nleaf, (const float *)M, piv, o, s, sel);
-    return launch_solve_rr<double, 1>(g, nleaf, (const double *)M, piv, o, s, sel);
+    if (fp32) return launch_solve_rr<float>(g, nleaf, (const float *)M, piv, o, s, sel);
+    return launch_solve_rr<double>(g, nleaf, (const double *)M, piv, o, s, sel);
   }
   if (fp32) return launch_trisolve<float, 1>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
   return launch_trisolve<double, 1>(g, nleaf, (double *)M, piv, rstep, o, s, sel);
