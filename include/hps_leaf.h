@@ -174,9 +174,9 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
  * chosen automatically):
  *   factor_variant : 0 automatic, 1 one 16-column panel per trailing pass,
  *                    2 panels in pairs (one trailing pass per 32 columns;
- *                    both panels in LDS when (p-2)^2 <= 256, else the
- *                    first panel's multipliers re-read from the work
- *                    matrix), 3 the whole work matrix held in registers
+ *                    both panels in LDS when (p-2)^2 <= 256 (FP64: < 256),
+ *                    else the first panel's multipliers re-read from the
+ *                    work matrix), 3 the whole work matrix held in registers
  *                    (HPS_FP32_REFINE and p <= 16 only; elsewhere the
  *                    automatic choice).  Automatic is 2, except 1 for
  *                    HPS_FP32_REFINE when 256 < (p-2)^2 < 400.

@@ -2867,14 +2867,17 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
     const hipError_t e = launch_factor_rr(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     if (e != hipErrorNotSupported) return e;
   }
-  const bool pairs = g.R <= 256 && g.tune_variant != 1 && factor_pairs_enabled();
+  // An FP64 work matrix of 256 rows (p = 18) already pairs faster with one
+  // panel in LDS (9.5 vs 12.0 ms for 4096 leaves), as do all larger ones.
+  const bool large = g.R > 256 || (!fp32 && g.R == 256);
+  const bool pairs = !large && g.tune_variant != 1 && factor_pairs_enabled();
   if (pairs) {
     if (fp32) return launch_factor2<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     return launch_factor2<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
   }
   // FP32 work matrices below 400 rows run two single-panel workgroups per CU
   // without spills and gain nothing from pairs (measured at p = 19, 20)
-  if (g.R > 256 && factor_pairs_enabled() &&
+  if (large && factor_pairs_enabled() &&
       (g.tune_variant == 2 || (g.tune_variant == 0 && (!fp32 || g.R >= 400)))) {
     if (fp32) return launch_factorP<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     return launch_factorP<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);

@@ -155,11 +155,12 @@ def test_condense_fp32_register_resident(torch, p):
 # multipliers re-read from the work matrix (variant 2), at both occupancies
 # (64 and 128 column chunks select one or two workgroups per CU), with an
 # even and an odd number of row tiles (p = 23: 28 tiles; p = 20, 32: odd),
-# and the single-panel variant on an even tile count.
+# the single-panel variant on an even tile count, and the FP64 default at
+# exactly 256 rows (p = 18), which takes the one-panel-in-LDS pairs.
 @pytest.mark.parametrize("p,prec,variant,chunk", [
     (23, hps.HPS_FP64, 2, 0), (23, hps.HPS_FP32_REFINE, 2, 0), (20, hps.HPS_FP64, 2, 64),
     (20, hps.HPS_FP32_REFINE, 2, 0), (32, hps.HPS_FP32_REFINE, 2, 128), (32, hps.HPS_FP64, 2, 64),
-    (26, hps.HPS_FP64, 1, 0)])
+    (26, hps.HPS_FP64, 1, 0), (18, hps.HPS_FP64, 0, 0)])
 def test_condense_large_factor_variants(torch, p, prec, variant, chunk):
     _say(f"condense large p={p} prec={prec} variant={variant} chunk={chunk}")
     prob = _small(p, 2)
