@@ -143,3 +143,65 @@ def test_planted_flux_sign_breaks_brute_force_agreement(monkeypatch):
     monkeypatch.setattr(lf, "operator", bad)
     prob = inputs.tiny(p=10)
     assert itf.relerr_true(itf.solve(prob), prob) > 1e-2
+
+
+# --------------------------------------------------------------------------
+# the error measures of eq. (accuracy_formula), pinned by hand-computed cases
+# --------------------------------------------------------------------------
+def test_relerr_res_hand_computed():
+    A = np.array([[2.0, 0.0], [0.0, 4.0]])
+    b = np.array([2.0, 4.0])
+    # A u - b = (0, 2), ||b|| = sqrt(20)
+    assert itf.relerr_res(A, b, np.array([1.0, 1.5])) == pytest.approx(2.0 / math.sqrt(20.0),
+                                                                       rel=1e-15)
+    assert itf.relerr_res(A, b, np.array([1.0, 1.0])) == 0.0
+    # u = 0 leaves the whole right-hand side: exactly 1 (not ||b|| = sqrt(61))
+    A2 = np.array([[1.0, 2.0], [3.0, 4.0]])
+    assert itf.relerr_res(A2, np.array([5.0, 6.0]), np.zeros(2)) == pytest.approx(1.0, rel=1e-15)
+
+
+def _two_leaf_solution(uedge, uint):
+    num = itf.numbering(2, 1, 4)
+    return itf.Solution(uedge=np.asarray(uedge, dtype=float),
+                        uint=np.asarray(uint, dtype=float).reshape(2, 4), num=num)
+
+
+def test_relerr_true_counts_every_non_corner_node_once():
+    """2 x 1 leaves, p = 4: 14 edge nodes (6 on the three vertical lines,
+    8 on the four horizontal leaf edges; the shared edge once, no corners)
+    and 2 x 4 interior nodes, 22 in all.  With u_true == 2 the denominator is
+    2 sqrt(22); one edge value off by 3 and one interior value off by -2 give
+    sqrt(13) / (2 sqrt(22))."""
+    prob = inputs.Problem(name="const", nx=2, ny=1, p=4, kappa=0.0,
+                          exact=lambda x, y, xp: xp.zeros_like(x) + 2.0)
+    num = itf.numbering(2, 1, 4)
+    assert num.nedge == 14
+    uedge = np.full(14, 2.0)
+    uedge[5] += 3.0
+    uint = np.full(8, 2.0)
+    uint[6] -= 2.0
+    err = itf.relerr_true(_two_leaf_solution(uedge, uint), prob)
+    assert err == pytest.approx(math.sqrt(13.0) / (2.0 * math.sqrt(22.0)), rel=1e-14)
+    assert itf.relerr_true(_two_leaf_solution(np.full(14, 2.0), np.full(8, 2.0)), prob) == 0.0
+
+
+def test_relerr_true_uses_the_node_coordinates():
+    """u_true = x1 on the same grid.  Chebyshev points of p = 4 on [-1, 1] are
+    -1, -1/2, 1/2, 1, so the leaf x-nodes are 0, 1/8, 3/8, 1/2 and
+    1/2, 5/8, 7/8, 1.  Sum of x1^2 over the 22 nodes:
+      interiors  2 (1/64 + 9/64) + 2 (25/64 + 49/64) = 168/64,
+      vertical lines x = 0, 1/2, 1 (2 nodes each)    = 2 (0 + 1/4 + 1) = 160/64,
+      horizontal edges (bottom and top of each leaf)  = 168/64,
+    in all 496/64 = 7.75.  One interior value off by 1/2 gives
+    (1/2) / sqrt(7.75)."""
+    prob = inputs.Problem(name="lin", nx=2, ny=1, p=4, kappa=0.0,
+                          exact=lambda x, y, xp: x + 0.0 * y)
+    num = itf.numbering(2, 1, 4)
+    xe, _ = itf.edge_coordinates(prob, num)
+    I = lf.flat(4, lf.interior_nodes(4))
+    uint = np.stack([lf.grid(box, 4)[0][I] for box in prob.boxes()])
+    assert np.sum(xe ** 2) + np.sum(uint ** 2) == pytest.approx(7.75, rel=1e-15)
+    uint_bad = uint.copy()
+    uint_bad[1, 2] += 0.5
+    err = itf.relerr_true(_two_leaf_solution(xe, uint_bad.ravel()), prob)
+    assert err == pytest.approx(0.5 / math.sqrt(7.75), rel=1e-14)
