@@ -101,10 +101,18 @@ hps_status hps_ctx_destroy(hps_ctx *ctx);
 
 /* Set up a batch of leaf groups: validates the descriptors, builds the
  * Chebyshev tables for each order (Sec. 2: p x p Chebyshev grid and spectral
- * differentiation) and allocates the batch's device workspace (LU workspace
- * for the leaves in flight, the FP64 X and h kept for recovery).  The
- * descriptor arrays are only read when the batch is used, so they must stay
- * valid for the batch's lifetime.  Synchronous. */
+ * differentiation) and allocates every device buffer the batch will use: the
+ * FP64 X and h kept for recovery, per-leaf flags, and the pass scratch (LU
+ * work matrices, pivots, refinement bookkeeping) of the leaves in flight,
+ * sized once for the largest mode (FP64 with a body-load column) within the
+ * workspace cap (environment HPS_WORKSPACE_MB, default 16 GiB; larger groups
+ * are condensed in several passes).  After this call no entry point of the
+ * batch allocates or frees device memory, so condense and recover calls may
+ * be captured in a HIP graph.  Groups are dealt to up to four lanes (largest
+ * work first), each with its own stream and scratch, so that groups of
+ * different orders run concurrently.  The descriptor arrays are only read
+ * when the batch is used, so they must stay valid for the batch's lifetime.
+ * Synchronous. */
 hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups,
                           hps_batch **out);
 
@@ -192,6 +200,15 @@ hps_status hps_batch_set_tuning(hps_batch *b, int g, int factor_variant, int chu
  *   h  : device [total leaves][ni]
  * Either may be NULL.  Async. */
 hps_status hps_batch_export(hps_batch *b, double *Xt, double *h);
+
+/* Per-leaf record of the last condense: flags device [total leaves] gets 1
+ * for every leaf the FP32 + refinement path handed to the FP64 redo (its
+ * refinement could not meet tol within max_refine corrections), else 0.
+ * Async. */
+hps_status hps_batch_redo_flags(hps_batch *b, int *flags);
+
+/* Number of lanes (concurrent streams) the batch's groups were dealt to. */
+int hps_batch_lanes(const hps_batch *b);
 
 /* Statistics of the last hps_leaf_condense (host pointers, either may be
  * NULL): the refinement step limit it ran with, and the number of leaves the

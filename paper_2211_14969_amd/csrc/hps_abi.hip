@@ -1,5 +1,18 @@
 // C ABI of the batched HPS leaf library: argument checking, batch and
-// workspace management, and the order of kernel launches.
+// scratch management, and the order of kernel launches.
+//
+// Memory: every device buffer a batch uses is allocated once, in
+// hps_leaf_build (the Chebyshev tables, the stored X and h, per-leaf flags,
+// and per-lane pass scratch sized for the largest mode: FP64 with a body-load
+// column).  hps_leaf_condense and hps_leaf_recover never allocate or free, so
+// they may be captured in a HIP graph after the batch is built.
+//
+// Concurrency: the order groups of a batch are dealt to up to kMaxLanes
+// lanes (largest work first, each lane taking the next group while its sum
+// of work is the smallest).  Each lane owns a side stream and its own pass
+// scratch; a condense forks the lanes from the context stream with an event
+// and joins them back, so groups of different orders overlap on the GPU
+// (and in a captured graph the lanes become parallel branches).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +40,8 @@ struct hps_ctx {
 
 namespace {
 
+constexpr int kMaxLanes = 4;
+
 struct Group {
   hps_leaf_desc d;
   hps::Geom geom;       // base pointers (leaf 0 of the group)
@@ -38,6 +53,30 @@ struct Group {
   double *dtab;         // device: t [p], D [p*p], D2 [p*p]
   int tune_variant;     // see hps_batch_set_tuning
   int tune_ch;
+  double work;          // algorithmic FLOP of the group (lane dealing)
+};
+
+// Device scratch of one pass over the leaves of a group: the LU work
+// matrices, pivots and retire steps of the leaves in flight, and the
+// refinement bookkeeping of those leaves (pass-local indexing).
+struct Scratch {
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  int *piv = nullptr, *rstep = nullptr;
+  size_t pr_elems = 0;      // ints in piv and in rstep
+  int *conv = nullptr;      // [max_leaves]
+  double *norms = nullptr;  // [max_leaves][kNormStride]
+  int *list = nullptr;      // [max_leaves]
+  int *count = nullptr;     // [1]
+  size_t max_leaves = 0;
+};
+
+struct Lane {
+  std::vector<int> groups;  // indices into hps_batch::groups, largest work first
+  Scratch sc;
+  void *mem = nullptr;      // the lane's single allocation (sc points into it)
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
 };
 
 hps_status from_hip(hipError_t e) {
@@ -63,17 +102,18 @@ hipEvent_t take_event(hps_ctx *c) {
   return e;
 }
 
-// Runs `launch` on the context stream, bracketed by events when timing.
+// Runs `launch` (which enqueues on stream s), bracketed by events when the
+// context is timing; timing only happens on the context stream.
 template <typename F>
-hipError_t timed(hps_ctx *c, int phase, F &&launch) {
-  if (!c->timing) return launch();
+hipError_t timed(hps_ctx *c, hipStream_t s, int phase, F &&launch) {
+  if (!c->timing || s != c->stream) return launch();
   hipEvent_t a = take_event(c), b = take_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
-  hipError_t e = hipEventRecord(a, c->stream);
+  hipError_t e = hipEventRecord(a, s);
   if (e != hipSuccess) return e;
   e = launch();
   if (e != hipSuccess) return e;
-  e = hipEventRecord(b, c->stream);
+  e = hipEventRecord(b, s);
   if (e != hipSuccess) return e;
   c->recs.push_back({phase, a, b});
   return hipSuccess;
@@ -85,14 +125,18 @@ size_t env_workspace_bytes() {
     const long long mb = std::atoll(s);
     if (mb > 0) return (size_t)mb << 20;
   }
-  return (size_t)16 << 30;  // 16 GiB of in-flight LU workspace
+  return (size_t)16 << 30;  // 16 GiB of in-flight LU work matrices in total
 }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
 struct hps_batch {
   hps_ctx *ctx = nullptr;
   std::vector<Group> groups;
+  std::vector<Lane> lanes;
+  hipEvent_t fork = nullptr;
   int nleaf = 0;
   size_t xt_total = 0, h_total = 0, s_total = 0, b_total = 0;
   double *Xt = nullptr;     // FP64 X^T of every leaf
@@ -100,15 +144,8 @@ struct hps_batch {
   bool have_h = false;
   bool have_x = false;
   int *info = nullptr;      // [nleaf] internal per-leaf status
-  int *conv = nullptr;      // [nleaf] refinement converged flags
-  double *norms = nullptr;  // [nleaf][kNormStride] refinement norms
-  int *list = nullptr;      // [nleaf] leaves to redo in FP64
-  int *count = nullptr;     // [2] length of list; leaves redone in FP64 by
-                            //     the last condense
-  void *ws = nullptr;       // LU work matrices of the leaves in flight
-  size_t ws_bytes = 0;
-  int *piv = nullptr, *rstep = nullptr;
-  size_t pr_elems = 0;
+  int *redo = nullptr;      // [nleaf] 1: condensed again in FP64 by the last condense
+  int *redo_total = nullptr;  // [1] leaves redone by the last condense
   size_t ws_limit = 0;
   int last_refine = 0;
 };
@@ -162,43 +199,15 @@ hps::Geom shift(const hps::Geom &g, int l0) {
   return s;
 }
 
-// Right-hand-side columns of the work matrix: the nb columns of A_ib plus
-// f_i when present, or the single column f_i - A_ib u_b when re-factoring.
-int rhs_cols(const Group &G, bool refactor, int extra) {
-  return refactor ? 1 : G.geom.nb + extra;
-}
-
-hps_status ensure_workspace(hps_batch *b, bool refactor, int extra, bool fp32,
-                            int *chunk_out) {
-  // chunk size per group so that the in-flight work matrices fit ws_limit
-  size_t need = 0, need_pr = 0;
-  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-    const Group &G = b->groups[gi];
-    const hps::Geom g = make_geom(G, rhs_cols(G, refactor, extra));
-    const size_t per = work_bytes_per_leaf(g, fp32);
-    size_t chunk = std::max<size_t>(1, b->ws_limit / per);
-    chunk = std::min<size_t>(chunk, (size_t)G.d.nleaf);
-    chunk_out[gi] = (int)chunk;
-    need = std::max(need, chunk * per);
-    need_pr = std::max(need_pr, chunk * (size_t)g.R);
-  }
-  if (need > b->ws_bytes) {
-    if (b->ws) HPS_TRY(hipFree(b->ws));
-    b->ws = nullptr;
-    b->ws_bytes = 0;
-    HPS_TRY(hipMalloc(&b->ws, need));
-    b->ws_bytes = need;
-  }
-  if (need_pr > b->pr_elems) {
-    if (b->piv) HPS_TRY(hipFree(b->piv));
-    if (b->rstep) HPS_TRY(hipFree(b->rstep));
-    b->piv = b->rstep = nullptr;
-    b->pr_elems = 0;
-    HPS_TRY(hipMalloc(&b->piv, need_pr * sizeof(int)));
-    HPS_TRY(hipMalloc(&b->rstep, need_pr * sizeof(int)));
-    b->pr_elems = need_pr;
-  }
-  return HPS_OK;
+// Leaves per pass of group g for a condense / recover that needs `per`
+// bytes of work matrix per leaf, within the scratch s.
+int pass_leaves(const Scratch &s, const hps::Geom &g, size_t per, int nleaf) {
+  if (!s.ws || per == 0) return 0;
+  size_t n = s.ws_bytes / per;
+  n = std::min(n, s.max_leaves);
+  n = std::min(n, s.pr_elems / (size_t)g.R);
+  n = std::min(n, (size_t)nleaf);
+  return (int)n;
 }
 
 hps_status sync_status(hps_batch *b, const int *info_dev, int n) {
@@ -214,6 +223,200 @@ hps_status sync_status(hps_batch *b, const int *info_dev, int n) {
   if (sing) return HPS_ERR_SINGULAR;
   if (nonf) return HPS_ERR_NONFINITE;
   if (nc) return HPS_ERR_NOT_CONVERGED;
+  return HPS_OK;
+}
+
+struct CondenseArgs {
+  bool fp32;
+  double tol;
+  int nref;
+  const double *f;
+  double *S;
+  double *w;
+};
+
+// Steps a2-a6 for every leaf of group G on stream s, in passes that fit the
+// scratch sc.
+hps_status condense_group(hps_batch *b, const Group &G, const Scratch &sc, hipStream_t s,
+                          const CondenseArgs &a) {
+  const int extra = a.f ? 1 : 0;
+  const hps::Geom g0 = make_geom(G, G.geom.nb + extra);
+  const int chunk = pass_leaves(sc, g0, work_bytes_per_leaf(g0, a.fp32), G.d.nleaf);
+  if (chunk < 1) return HPS_ERR_INVALID;
+  for (int l0 = 0; l0 < G.d.nleaf; l0 += chunk) {
+    const int n = std::min(chunk, G.d.nleaf - l0);
+    const hps::Geom g = shift(g0, l0);
+    const int gl = G.leaf0 + l0;
+    const double *fc = a.f ? a.f + G.h_off + (size_t)l0 * g.ni : nullptr;
+    double *Xt = b->Xt + G.xt_off + (size_t)l0 * g.nb * g.ni;
+    double *hh = a.f ? b->h + G.h_off + (size_t)l0 * g.ni : nullptr;
+    int *inf = b->info + gl;
+    HPS_TRY(timed(b->ctx, s, 1, [&] {
+      return hps::launch_factor(g, n, a.fp32, sc.ws, sc.piv, sc.rstep, inf, hps::RHS_CONDENSE, fc,
+                                nullptr, s);
+    }));
+    hps::BackOut o;
+    o.Xt = Xt;
+    o.h = hh;
+    o.ui = nullptr;
+    o.norms = nullptr;
+    o.skip = nullptr;
+    o.mode = hps::BACK_STORE;
+    HPS_TRY(timed(b->ctx, s, 2, [&] {
+      return hps::launch_backsolve(g, n, a.fp32, sc.ws, sc.piv, sc.rstep, o, s);
+    }));
+    if (a.fp32) {
+      // FP64 iterative refinement: residual -> stop test -> FP32 correction,
+      // and one more residual after the last correction for the final test.
+      int *conv = sc.conv;
+      double *nrm = sc.norms;
+      const double tl = a.tol > 0.0 ? a.tol : 1e-10;
+      HPS_TRY(hps::launch_fill_int(conv, n, 0, s));
+      o.mode = hps::BACK_ACCUM;
+      o.skip = conv;
+      o.norms = nrm;
+      int nsol = 1;   // column chunks of the previous correction solve
+      for (int it = 0; it <= a.nref; ++it) {
+        if (it == a.nref && it > 0 && tl >= 1.0) break;  // no final test wanted
+        const int nch = hps::refine_chunks(g, it);
+        HPS_TRY(timed(b->ctx, s, 6, [&] {
+          return hps::launch_residual(g, n, (float *)sc.ws, Xt, hh, fc, conv, nrm, nch, s);
+        }));
+        HPS_TRY(timed(b->ctx, s, 3, [&] {
+          return hps::launch_convcheck(n, nrm, tl, conv, inf, it, it == a.nref ? 1 : 0, nch, nsol,
+                                       s);
+        }));
+        if (it == a.nref) break;
+        HPS_TRY(timed(b->ctx, s, 3, [&] {
+          return hps::launch_refine_solve(g, n, sc.ws, sc.piv, sc.rstep, o, nch, s);
+        }));
+        nsol = nch;
+      }
+      // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
+      // for an FP32 factorisation, e.g. near a leaf resonance) are condensed
+      // again in FP64, reusing the FP32 work matrices, in passes of `cap`.
+      HPS_TRY(hps::launch_fill_int(sc.count, 1, 0, s));
+      HPS_TRY(timed(b->ctx, s, 3, [&] {
+        return hps::launch_collect(n, inf, sc.list, sc.count, b->redo_total, b->redo + gl, s);
+      }));
+      const size_t per64 = work_bytes_per_leaf(g, false);
+      const int cap = pass_leaves(sc, g, per64, n);
+      if (cap < 1) return HPS_ERR_INVALID;
+      hps::BackOut o64;
+      o64.Xt = Xt;
+      o64.h = hh;
+      o64.ui = nullptr;
+      o64.norms = nullptr;
+      o64.skip = nullptr;
+      o64.mode = hps::BACK_STORE;
+      for (int s0 = 0; s0 < n; s0 += cap) {
+        hps::Sel sel;
+        sel.list = sc.list;
+        sel.count = sc.count;
+        sel.slot0 = s0;
+        const int nb_ = std::min(cap, n - s0);
+        HPS_TRY(timed(b->ctx, s, 7, [&] {
+          return hps::launch_factor(g, nb_, false, sc.ws, sc.piv, sc.rstep, inf,
+                                    hps::RHS_CONDENSE, fc, nullptr, s, sel);
+        }));
+        HPS_TRY(timed(b->ctx, s, 7, [&] {
+          return hps::launch_backsolve(g, nb_, false, sc.ws, sc.piv, sc.rstep, o64, s, sel);
+        }));
+      }
+    }
+    HPS_TRY(timed(b->ctx, s, 4, [&] {
+      return hps::launch_schur(g, n, Xt, hh, a.S + G.s_off + (size_t)l0 * g.nb * g.nb,
+                               a.w ? a.w + G.b_off + (size_t)l0 * g.nb : nullptr, inf, s);
+    }));
+  }
+  return HPS_OK;
+}
+
+// Re-form and re-factor every leaf of group G in FP64 and solve
+// A_ii u_i = f_i - A_ib u_b, in passes that fit the scratch sc.
+hps_status refactor_group(hps_batch *b, const Group &G, const Scratch &sc, hipStream_t s,
+                          const double *ub, const double *f, double *ui) {
+  const hps::Geom g0 = make_geom(G, 1);
+  const int ch = pass_leaves(sc, g0, work_bytes_per_leaf(g0, false), G.d.nleaf);
+  if (ch < 1) return HPS_ERR_INVALID;
+  for (int l0 = 0; l0 < G.d.nleaf; l0 += ch) {
+    const int n = std::min(ch, G.d.nleaf - l0);
+    const hps::Geom g = shift(g0, l0);
+    const double *fc = f ? f + G.h_off + (size_t)l0 * g.ni : nullptr;
+    const double *uc = ub + G.b_off + (size_t)l0 * g.nb;
+    int *inf = b->info + G.leaf0 + l0;
+    HPS_TRY(timed(b->ctx, s, 5, [&] {
+      return hps::launch_factor(g, n, false, sc.ws, sc.piv, sc.rstep, inf, hps::RHS_REFACTOR, fc,
+                                uc, s);
+    }));
+    hps::BackOut o;
+    o.Xt = nullptr;
+    o.h = nullptr;
+    o.ui = ui + G.h_off + (size_t)l0 * g.ni;
+    o.norms = nullptr;
+    o.skip = nullptr;
+    o.mode = hps::BACK_UI;
+    HPS_TRY(timed(b->ctx, s, 5, [&] {
+      return hps::launch_backsolve(g, n, false, sc.ws, sc.piv, sc.rstep, o, s);
+    }));
+  }
+  return HPS_OK;
+}
+
+// Runs `body(lane, stream)` for every lane: serially on the context stream
+// when there is one lane or the context is timing (so that phase times stay
+// attributable), else each lane on its own stream, forked from and joined
+// back into the context stream.
+template <typename F>
+hps_status run_lanes(hps_batch *b, F &&body) {
+  hipStream_t s0 = b->ctx->stream;
+  const bool serial = b->lanes.size() == 1 || b->ctx->timing;
+  if (serial) {
+    for (Lane &L : b->lanes) {
+      const hps_status st = body(L, s0);
+      if (st != HPS_OK) return st;
+    }
+    return HPS_OK;
+  }
+  HPS_TRY(hipEventRecord(b->fork, s0));
+  for (Lane &L : b->lanes) HPS_TRY(hipStreamWaitEvent(L.stream, b->fork, 0));
+  hps_status first = HPS_OK;
+  for (Lane &L : b->lanes) {
+    const hps_status st = body(L, L.stream);
+    if (st != HPS_OK && first == HPS_OK) first = st;
+    // join even after a failure, so no branch is left dangling in a capture
+    HPS_TRY(hipEventRecord(L.done, L.stream));
+    HPS_TRY(hipStreamWaitEvent(s0, L.done, 0));
+  }
+  return first;
+}
+
+hps_status check_condense_args(hps_batch *b, hps_precision prec, int max_refine, const double *S,
+                               const double *f) {
+  if (!b || !S) return HPS_ERR_INVALID;
+  if (prec != HPS_FP64 && prec != HPS_FP32_REFINE) return HPS_ERR_INVALID;
+  if (max_refine < 0 || max_refine > 16) return HPS_ERR_INVALID;
+  const bool fp32 = prec == HPS_FP32_REFINE;
+  const int extra = f ? 1 : 0;
+  for (const Group &G : b->groups)
+    if (hps::factor_lds_bytes(make_geom(G, G.geom.nb + extra), fp32) == 0) return HPS_ERR_INVALID;
+  return HPS_OK;
+}
+
+hps_status condense_prologue(hps_batch *b) {
+  hipStream_t s = b->ctx->stream;
+  HPS_TRY(hps::launch_fill_int(b->redo, b->nleaf, 0, s));
+  HPS_TRY(hps::launch_fill_int(b->redo_total, 1, 0, s));
+  return HPS_OK;
+}
+
+hps_status condense_epilogue(hps_batch *b, int nref, const double *f, int *info, int flags) {
+  b->have_x = true;
+  b->have_h = f != nullptr;
+  b->last_refine = nref;
+  hipStream_t s = b->ctx->stream;
+  if (info) HPS_TRY(hps::launch_copy_info(b->info, info, b->nleaf, s));
+  if (flags & HPS_SYNC) return sync_status(b, b->info, b->nleaf);
   return HPS_OK;
 }
 
@@ -301,16 +504,17 @@ hps_status hps_batch_destroy(hps_batch *b) {
     if (p && hipFree(p) != hipSuccess) st = HPS_ERR_HIP;
   };
   for (Group &G : b->groups) fr(G.dtab);
+  for (Lane &L : b->lanes) {
+    fr(L.mem);
+    if (L.stream && hipStreamDestroy(L.stream) != hipSuccess) st = HPS_ERR_HIP;
+    if (L.done && hipEventDestroy(L.done) != hipSuccess) st = HPS_ERR_HIP;
+  }
+  if (b->fork && hipEventDestroy(b->fork) != hipSuccess) st = HPS_ERR_HIP;
   fr(b->Xt);
   fr(b->h);
   fr(b->info);
-  fr(b->conv);
-  fr(b->norms);
-  fr(b->list);
-  fr(b->count);
-  fr(b->ws);
-  fr(b->piv);
-  fr(b->rstep);
+  fr(b->redo);
+  fr(b->redo_total);
   delete b;
   return st;
 }
@@ -354,6 +558,8 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
       break;
     }
     G.geom = make_geom(G.d, G.dtab, 4 * (p - 2));
+    const double ni = G.geom.ni, nb = G.geom.nb;
+    G.work = G.d.nleaf * ((2.0 / 3.0) * ni * ni * ni + 2.0 * ni * ni * nb);
     G.xt_off = b->xt_total;
     G.h_off = b->h_total;
     G.s_off = b->s_total;
@@ -370,11 +576,76 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
     if (hipMalloc(&b->Xt, sizeof(double) * b->xt_total) != hipSuccess ||
         hipMalloc(&b->h, sizeof(double) * b->h_total) != hipSuccess ||
         hipMalloc(&b->info, sizeof(int) * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->conv, sizeof(int) * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->norms, sizeof(double) * hps::kNormStride * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->list, sizeof(int) * b->nleaf) != hipSuccess ||
-        hipMalloc(&b->count, 2 * sizeof(int)) != hipSuccess)
+        hipMalloc(&b->redo, sizeof(int) * b->nleaf) != hipSuccess ||
+        hipMalloc(&b->redo_total, sizeof(int)) != hipSuccess)
       st = HPS_ERR_OOM;
+  }
+  if (st == HPS_OK) {
+    // deal the groups to lanes: largest work first, to the least loaded lane
+    const int nl = std::min<int>(kMaxLanes, (int)b->groups.size());
+    b->lanes.resize(nl);
+    std::vector<int> order(b->groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->groups[x].work > b->groups[y].work; });
+    std::vector<double> load(nl, 0.0);
+    for (int gi : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->lanes[k].groups.push_back(gi);
+      load[k] += b->groups[gi].work;
+    }
+    // each lane's pass scratch, sized once for the largest mode: FP64 work
+    // matrices with a body-load column (FP32 passes then fit twice the
+    // leaves, whose bookkeeping is sized for that count)
+    const size_t lane_limit = std::max<size_t>(b->ws_limit / nl, 1);
+    for (Lane &L : b->lanes) {
+      size_t ws = 0, leaves = 0, prl = 0;
+      for (int gi : L.groups) {
+        const Group &G = b->groups[gi];
+        const hps::Geom g = make_geom(G, G.geom.nb + 1);
+        const size_t per64 = work_bytes_per_leaf(g, false);
+        const size_t n64 = std::min<size_t>(std::max<size_t>(1, lane_limit / per64), G.d.nleaf);
+        const size_t n32 = std::min<size_t>(2 * n64, G.d.nleaf);
+        ws = std::max(ws, n64 * per64);
+        leaves = std::max(leaves, n32);
+        prl = std::max(prl, n32 * (size_t)g.R);
+      }
+      // carve with ws_bytes = ws and piv/rstep/bookkeeping for `leaves`
+      const size_t bytes = ws + 2 * sizeof(int) * prl + sizeof(double) * hps::kNormStride * leaves +
+                           2 * sizeof(int) * leaves + 2 * sizeof(int) + 8 * 256;
+      if (hipMalloc(&L.mem, bytes) != hipSuccess) {
+        st = HPS_ERR_OOM;
+        break;
+      }
+      char *p = (char *)L.mem;
+      size_t off = 0;
+      auto take = [&](size_t n) {
+        off = align_up(off, 256);
+        char *q = p + off;
+        off += n;
+        return q;
+      };
+      L.sc.ws = take(ws);
+      L.sc.ws_bytes = ws;
+      L.sc.piv = (int *)take(sizeof(int) * prl);
+      L.sc.rstep = (int *)take(sizeof(int) * prl);
+      L.sc.pr_elems = prl;
+      L.sc.norms = (double *)take(sizeof(double) * hps::kNormStride * leaves);
+      L.sc.conv = (int *)take(sizeof(int) * leaves);
+      L.sc.list = (int *)take(sizeof(int) * leaves);
+      L.sc.count = (int *)take(sizeof(int) * 2);
+      L.sc.max_leaves = leaves;
+      if (nl > 1) {
+        if (hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&L.done, hipEventDisableTiming) != hipSuccess) {
+          st = HPS_ERR_HIP;
+          break;
+        }
+      }
+    }
+    if (st == HPS_OK && nl > 1 &&
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+      st = HPS_ERR_HIP;
   }
   if (st != HPS_OK) {
     hps_batch_destroy(b);
@@ -414,111 +685,21 @@ hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib, doub
 
 hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int max_refine,
                              const double *f, double *S, double *w, int *info, int flags) {
-  if (!b || !S) return HPS_ERR_INVALID;
-  if (prec != HPS_FP64 && prec != HPS_FP32_REFINE) return HPS_ERR_INVALID;
-  if (max_refine < 0 || max_refine > 16) return HPS_ERR_INVALID;
-  const bool fp32 = prec == HPS_FP32_REFINE;
-  const int extra = f ? 1 : 0;
-  std::vector<int> chunk(b->groups.size());
-  for (const Group &G : b->groups)
-    if (hps::factor_lds_bytes(make_geom(G, G.geom.nb + extra), fp32) == 0)
-      return HPS_ERR_INVALID;
-  hps_status st = ensure_workspace(b, false, extra, fp32, chunk.data());
+  hps_status st = check_condense_args(b, prec, max_refine, S, f);
   if (st != HPS_OK) return st;
-  hipStream_t s = b->ctx->stream;
-  const int nref = fp32 ? max_refine : 0;
-  HPS_TRY(hps::launch_fill_int(b->count, 2, 0, s));
-  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-    const Group &G = b->groups[gi];
-    const hps::Geom g0 = make_geom(G, G.geom.nb + extra);
-    for (int l0 = 0; l0 < G.d.nleaf; l0 += chunk[gi]) {
-      const int n = std::min(chunk[gi], G.d.nleaf - l0);
-      const hps::Geom g = shift(g0, l0);
-      const int gl = G.leaf0 + l0;
-      const double *fc = f ? f + G.h_off + (size_t)l0 * g.ni : nullptr;
-      double *Xt = b->Xt + G.xt_off + (size_t)l0 * g.nb * g.ni;
-      double *hh = f ? b->h + G.h_off + (size_t)l0 * g.ni : nullptr;
-      int *inf = b->info + gl;
-      HPS_TRY(timed(b->ctx, 1, [&] {
-        return hps::launch_factor(g, n, fp32, b->ws, b->piv, b->rstep, inf, hps::RHS_CONDENSE, fc,
-                                  nullptr, s);
-      }));
-      hps::BackOut o;
-      o.Xt = Xt;
-      o.h = hh;
-      o.ui = nullptr;
-      o.norms = nullptr;
-      o.skip = nullptr;
-      o.mode = hps::BACK_STORE;
-      HPS_TRY(timed(b->ctx, 2, [&] { return hps::launch_backsolve(g, n, fp32, b->ws, b->piv, b->rstep, o, s); }));
-      if (fp32) {
-        // FP64 iterative refinement: residual -> stop test -> FP32 correction,
-        // and one more residual after the last correction for the final test.
-        int *conv = b->conv + gl;
-        double *nrm = b->norms + hps::kNormStride * (size_t)gl;
-        const double tl = tol > 0.0 ? tol : 1e-10;
-        HPS_TRY(hps::launch_fill_int(conv, n, 0, s));
-        o.mode = hps::BACK_ACCUM;
-        o.skip = conv;
-        o.norms = nrm;
-        int nsol = 1;   // column chunks of the previous correction solve
-        for (int it = 0; it <= nref; ++it) {
-          if (it == nref && it > 0 && tl >= 1.0) break;  // no final test wanted
-          const int nch = hps::refine_chunks(g, it);
-          HPS_TRY(timed(b->ctx, 6, [&] {
-            return hps::launch_residual(g, n, (float *)b->ws, Xt, hh, fc, conv, nrm, nch, s);
-          }));
-          HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_convcheck(n, nrm, tl, conv, inf, it, it == nref ? 1 : 0, nch, nsol,
-                                         s);
-          }));
-          if (it == nref) break;
-          HPS_TRY(timed(b->ctx, 3, [&] {
-            return hps::launch_refine_solve(g, n, b->ws, b->piv, b->rstep, o, nch, s);
-          }));
-          nsol = nch;
-        }
-        // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
-        // for an FP32 factorisation, e.g. near a leaf resonance) are condensed
-        // again in FP64, reusing the FP32 workspace, in passes of `cap` leaves.
-        HPS_TRY(hps::launch_fill_int(b->count, 1, 0, s));
-        HPS_TRY(timed(b->ctx, 3, [&] { return hps::launch_collect(n, inf, b->list, b->count, b->count + 1, s); }));
-        const size_t per64 = work_bytes_per_leaf(g, false);
-        const int cap = (int)std::max<size_t>(1, std::min<size_t>(b->ws_bytes / per64, n));
-        hps::BackOut o64;
-        o64.Xt = Xt;
-        o64.h = hh;
-        o64.ui = nullptr;
-        o64.norms = nullptr;
-        o64.skip = nullptr;
-        o64.mode = hps::BACK_STORE;
-        for (int s0 = 0; s0 < n; s0 += cap) {
-          hps::Sel sel;
-          sel.list = b->list;
-          sel.count = b->count;
-          sel.slot0 = s0;
-          const int nb_ = std::min(cap, n - s0);
-          HPS_TRY(timed(b->ctx, 7, [&] {
-            return hps::launch_factor(g, nb_, false, b->ws, b->piv, b->rstep, inf,
-                                      hps::RHS_CONDENSE, fc, nullptr, s, sel);
-          }));
-          HPS_TRY(timed(b->ctx, 7, [&] {
-            return hps::launch_backsolve(g, nb_, false, b->ws, b->piv, b->rstep, o64, s, sel);
-          }));
-        }
-      }
-      HPS_TRY(timed(b->ctx, 4, [&] {
-        return hps::launch_schur(g, n, Xt, hh, S + G.s_off + (size_t)l0 * g.nb * g.nb,
-                                 w ? w + G.b_off + (size_t)l0 * g.nb : nullptr, inf, s);
-      }));
+  const bool fp32 = prec == HPS_FP32_REFINE;
+  const CondenseArgs a{fp32, tol, fp32 ? max_refine : 0, f, S, w};
+  st = condense_prologue(b);
+  if (st != HPS_OK) return st;
+  st = run_lanes(b, [&](Lane &L, hipStream_t s) {
+    for (int gi : L.groups) {
+      const hps_status e = condense_group(b, b->groups[gi], L.sc, s, a);
+      if (e != HPS_OK) return e;
     }
-  }
-  b->have_x = true;
-  b->have_h = f != nullptr;
-  b->last_refine = nref;
-  if (info) HPS_TRY(hps::launch_copy_info(b->info, info, b->nleaf, s));
-  if (flags & HPS_SYNC) return sync_status(b, b->info, b->nleaf);
-  return HPS_OK;
+    return HPS_OK;
+  });
+  if (st != HPS_OK) return st;
+  return condense_epilogue(b, a.nref, f, info, flags);
 }
 
 hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, double *ui,
@@ -526,41 +707,20 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
   if (!b || !ub || !ui) return HPS_ERR_INVALID;
   hipStream_t s = b->ctx->stream;
   if (flags & HPS_RECOVER_REFACTOR) {
-    std::vector<int> chunk(b->groups.size());
-    hps_status st = ensure_workspace(b, true, 0, false, chunk.data());
-    if (st != HPS_OK) return st;
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-      const Group &G = b->groups[gi];
-      const hps::Geom g0 = make_geom(G, 1);
-      const int ch = chunk[gi];
-      for (int l0 = 0; l0 < G.d.nleaf; l0 += ch) {
-        const int n = std::min(ch, G.d.nleaf - l0);
-        const hps::Geom g = shift(g0, l0);
-        const double *fc = f ? f + G.h_off + (size_t)l0 * g.ni : nullptr;
-        const double *uc = ub + G.b_off + (size_t)l0 * g.nb;
-        int *inf = b->info + G.leaf0 + l0;
-        HPS_TRY(timed(b->ctx, 5, [&] {
-          return hps::launch_factor(g, n, false, b->ws, b->piv, b->rstep, inf, hps::RHS_REFACTOR,
-                                    fc, uc, s);
-        }));
-        hps::BackOut o;
-        o.Xt = nullptr;
-        o.h = nullptr;
-        o.ui = ui + G.h_off + (size_t)l0 * g.ni;
-        o.norms = nullptr;
-        o.skip = nullptr;
-        o.mode = hps::BACK_UI;
-        HPS_TRY(timed(b->ctx, 5, [&] {
-          return hps::launch_backsolve(g, n, false, b->ws, b->piv, b->rstep, o, s);
-        }));
+    hps_status st = run_lanes(b, [&](Lane &L, hipStream_t ls) {
+      for (int gi : L.groups) {
+        const hps_status e = refactor_group(b, b->groups[gi], L.sc, ls, ub, f, ui);
+        if (e != HPS_OK) return e;
       }
-    }
+      return HPS_OK;
+    });
+    if (st != HPS_OK) return st;
     if (flags & HPS_SYNC) return sync_status(b, b->info, b->nleaf);
     return HPS_OK;
   }
   if (!b->have_x) return HPS_ERR_INVALID;
   for (const Group &G : b->groups) {
-    HPS_TRY(timed(b->ctx, 5, [&] {
+    HPS_TRY(timed(b->ctx, s, 5, [&] {
       return hps::launch_recover(G.geom, G.d.nleaf, b->Xt + G.xt_off,
                                  b->have_h ? b->h + G.h_off : nullptr, ub + G.b_off,
                                  ui + G.h_off, s);
@@ -593,16 +753,24 @@ hps_status hps_batch_export(hps_batch *b, double *Xt, double *h) {
   return HPS_OK;
 }
 
+hps_status hps_batch_redo_flags(hps_batch *b, int *flags) {
+  if (!b || !flags) return HPS_ERR_INVALID;
+  HPS_TRY(hps::launch_copy_info(b->redo, flags, b->nleaf, b->ctx->stream));
+  return HPS_OK;
+}
+
 hps_status hps_batch_stats(const hps_batch *b, int *refine_steps, int *fp64_redo) {
   if (!b) return HPS_ERR_INVALID;
   if (refine_steps) *refine_steps = b->last_refine;
   if (fp64_redo) {
-    int v[2] = {0, 0};
+    int v = 0;
     HPS_TRY(hipStreamSynchronize(b->ctx->stream));
-    HPS_TRY(hipMemcpy(v, b->count, sizeof(v), hipMemcpyDeviceToHost));
-    *fp64_redo = v[1];
+    HPS_TRY(hipMemcpy(&v, b->redo_total, sizeof(int), hipMemcpyDeviceToHost));
+    *fp64_redo = v;
   }
   return HPS_OK;
 }
+
+int hps_batch_lanes(const hps_batch *b) { return b ? (int)b->lanes.size() : -1; }
 
 }  // extern "C"

@@ -86,7 +86,7 @@ hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int
 // correction solve; more than one only for iterations after the first,
 // where the few leaves left would otherwise leave the GPU idle
 int refine_chunks(const Geom &g, int it);
-hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total,
+hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total, int *redo,
                           hipStream_t s);
 hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h,
                         double *S, double *w, int *info, hipStream_t s);

@@ -2477,14 +2477,16 @@ __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int
   }
 }
 
-// Leaves whose refinement failed (info -1) are listed for an FP64 redo.
-__global__ void k_collect(int nleaf, int *info, int *list, int *count, int *total) {
+// Leaves whose refinement failed (info -1) are listed for an FP64 redo and
+// flagged in `redo` (indexed like `info`).
+__global__ void k_collect(int nleaf, int *info, int *list, int *count, int *total, int *redo) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaf || info[l] != -1) return;
   atomicAdd(total, 1);
   const int slot = atomicAdd(count, 1);
   list[slot] = l;
   info[l] = 0;
+  redo[l] = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -3076,10 +3078,11 @@ hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int
   return hipGetLastError();
 }
 
-hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total,
+hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total, int *redo,
                           hipStream_t s) {
+  if (nleaf <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_collect, dim3((nleaf + 255) / 256), dim3(256), 0, s, nleaf, info, list,
-                     count, total);
+                     count, total, redo);
   return hipGetLastError();
 }
 

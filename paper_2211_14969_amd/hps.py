@@ -36,6 +36,7 @@ EXPORTED = (
     "hps_batch_nleaf", "hps_batch_group_dims", "hps_leaf_nodes", "hps_leaf_operator",
     "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
     "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times", "hps_batch_set_tuning",
+    "hps_batch_redo_flags", "hps_batch_lanes",
 )
 
 HPS_NPHASE = 8
@@ -97,6 +98,10 @@ def load(path: str = LIB_PATH):
     L.hps_leaf_operator.argtypes = [vp, i, vp, vp, vp, vp]
     L.hps_leaf_condense.restype = i
     L.hps_leaf_condense.argtypes = [vp, i, d, i, vp, vp, vp, vp, i]
+    L.hps_batch_redo_flags.restype = i
+    L.hps_batch_redo_flags.argtypes = [vp, vp]
+    L.hps_batch_lanes.restype = i
+    L.hps_batch_lanes.argtypes = [vp]
     L.hps_leaf_recover.restype = i
     L.hps_leaf_recover.argtypes = [vp, vp, vp, vp, i]
     L.hps_batch_export.restype = i
@@ -210,6 +215,15 @@ def hps_leaf_condense(batch: int, prec: int, tol: float, max_refine: int, f, S, 
                                   _ptr(_f64(f, "f")), _ptr(_f64(S, "S")), _ptr(_f64(w, "w")),
                                   _ptr(info), int(flags))
     return _check(st, "hps_leaf_condense", allow)
+
+
+def hps_batch_redo_flags(batch: int, flags) -> None:
+    """flags: int32 device tensor [total leaves]."""
+    _check(load().hps_batch_redo_flags(ctypes.c_void_p(batch), _ptr(flags)), "hps_batch_redo_flags")
+
+
+def hps_batch_lanes(batch: int) -> int:
+    return load().hps_batch_lanes(ctypes.c_void_p(batch))
 
 
 def hps_leaf_recover(batch: int, ub, f, ui, flags: int = 0) -> None:

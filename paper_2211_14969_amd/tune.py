@@ -51,6 +51,21 @@ def candidates(p: int, prec: int = hps.HPS_FP64) -> List[Tuple[int, int]]:
     return out
 
 
+def tuning_problem(prob, max_leaves: int):
+    """The leading leaf rows of `prob` (at most `max_leaves` leaves) as a
+    problem of its own: the domain is cut in x2 so that every leaf keeps its
+    box, hence its conditioning and refinement behaviour."""
+    from .inputs import Problem
+    if prob.nleaf <= max_leaves:
+        return prob
+    ny = max(1, min(prob.ny, max_leaves // prob.nx))
+    x0, x1, y0, y1 = prob.domain
+    hy = (y1 - y0) / prob.ny
+    return Problem(name=prob.name + "_tune", nx=prob.nx, ny=ny, p=prob.p, kappa=prob.kappa,
+                   domain=(x0, x1, y0, y0 + ny * hy), coef=prob.coef, g=prob.g,
+                   exact=prob.exact, f=prob.f, meta=prob.meta)
+
+
 def load_cache(path: Optional[str]) -> Dict[str, list]:
     if path and os.path.exists(path):
         with open(path) as fh:
@@ -101,12 +116,7 @@ def tune_batch(lb, prec: int = hps.HPS_FP64, max_refine: int = 1, reps: int = 2,
             hps.hps_batch_set_tuning(lb.batch, gi, *setting)
             out[gi] = {"key": key, "setting": setting, "ms": cache[key]["ms"], "cached": True}
             continue
-        prob: Problem = G.problem
-        if prob.nleaf > max_leaves:
-            ny = max(1, max_leaves // prob.nx)
-            prob = Problem(name=prob.name + "_tune", nx=prob.nx, ny=min(ny, prob.ny), p=prob.p,
-                           kappa=prob.kappa, domain=prob.domain, coef=prob.coef, g=prob.g,
-                           exact=prob.exact, f=prob.f, meta=prob.meta)
+        prob: Problem = tuning_problem(G.problem, max_leaves)
         sub = LeafBatch([prob])
         timings = {}
         for setting in candidates(G.p, prec):

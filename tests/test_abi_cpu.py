@@ -61,6 +61,8 @@ def test_argument_validation_without_device(lib):
     assert lib.hps_batch_group_dims(None, 0, None, None, None, None) == hps.HPS_ERR_INVALID
     assert lib.hps_batch_nleaf(None) == -1
     assert lib.hps_batch_destroy(None) == hps.HPS_OK
+    assert lib.hps_batch_redo_flags(None, None) == hps.HPS_ERR_INVALID
+    assert lib.hps_batch_lanes(None) == -1
 
 
 @pytest.mark.parametrize("nx,ny,p", [(4, 4, 8), (3, 2, 5), (1, 1, 6), (5, 3, 12)])

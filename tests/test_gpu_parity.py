@@ -444,3 +444,121 @@ def test_workspace_chunking_matches_single_pass(torch, prec, monkeypatch):
     assert torch.equal(u1, u2)
     B1.close()
     B2.close()
+
+
+# --------------------------------------------------------------------------
+# concurrent lanes, redo flags, a leaf near a Dirichlet resonance
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+def test_lanes_match_serial_order(torch, prec):
+    """Groups of different orders condensed on concurrent lanes give the
+    same bits as the same groups one after another on the context stream
+    (the per-phase timing mode runs the lanes serially)."""
+    probs = [_small(p, 3) for p in (8, 12, 16, 20, 24, 30)]
+    _say(f"lanes vs serial prec={prec}")
+    B = _batch(probs)
+    assert hps.hps_batch_lanes(B.batch) == 4
+    S1, w1, i1, st = B.condense(prec=prec, max_refine=3, sync=True)
+    assert st == hps.HPS_OK
+    u_b = torch.randn(B.nb_total, dtype=torch.float64, device="cuda")
+    u1 = B.recover(u_b, refactor=True, sync=True)
+    hps.hps_ctx_set_timing(B.ctx, True)
+    S2, w2, i2, st = B.condense(prec=prec, max_refine=3, sync=True)
+    u2 = B.recover(u_b, refactor=True, sync=True)
+    hps.hps_ctx_phase_times(B.ctx)
+    hps.hps_ctx_set_timing(B.ctx, False)
+    assert torch.equal(S1, S2) and torch.equal(i1, i2) and torch.equal(u1, u2)
+    for G, Sg in zip(B.groups, B.split(S1, "S")):
+        for t in (0, G.nleaf - 1):
+            bl, c = oracle_leaf(G.problem, t)
+            tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+            assert relerr(Sg[t].cpu().numpy(), c.S) <= leaf_bar(bl.Aii, tol)
+    B.close()
+
+
+def test_redo_flags_follow_the_fallback(torch):
+    prob = _small(12, 2, 2)
+    B = _batch([prob])
+    S, w, info = B.alloc_outputs()
+    flags = torch.full((prob.nleaf,), 7, dtype=torch.int32, device="cuda")
+    hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 1e-300, 1, None, S, w, info, hps.HPS_SYNC)
+    hps.hps_batch_redo_flags(B.batch, flags)
+    torch.cuda.synchronize()
+    assert bool((flags == 1).all())
+    hps.hps_leaf_condense(B.batch, hps.HPS_FP32_REFINE, 0.0, 3, None, S, w, info, hps.HPS_SYNC)
+    hps.hps_batch_redo_flags(B.batch, flags)
+    torch.cuda.synchronize()
+    assert bool((flags == 0).all()) and hps.hps_batch_stats(B.batch)[1] == 0
+    hps.hps_leaf_condense(B.batch, hps.HPS_FP64, 0.0, 3, None, S, w, info, hps.HPS_SYNC)
+    hps.hps_batch_redo_flags(B.batch, flags)
+    torch.cuda.synchronize()
+    assert bool((flags == 0).all())
+    B.close()
+
+
+def _near_resonant_problem(p=16, h=0.125, target_cond=1e8):
+    """Two leaves of side h with b == 1: on the left one kappa^2 sits just
+    above the smallest eigenvalue lambda_1 of the discrete Dirichlet operator
+    (A_ii at kappa = 0), so A_ii(kappa) = A_ii(0) - kappa^2 I is nearly
+    singular (cond ~ target_cond); on the right one kappa^2 = lambda_1 / 2."""
+    box = (0.0, h, 0.0, h)
+    bl0 = lf.blocks(box, p, {})
+    lam = np.linalg.eigvals(bl0.Aii)
+    lam1 = float(np.min(lam.real))
+    lo, hi = 0.0, 1e-2              # bisection on the relative offset
+    for _ in range(60):
+        d = 0.5 * (lo + hi) if hi > 0 else lo
+        k2 = lam1 * (1.0 + d)
+        c = np.linalg.cond(bl0.Aii - k2 * np.eye(bl0.Aii.shape[0]))
+        if c > target_cond:
+            lo = d
+        else:
+            hi = d
+    k2_left = lam1 * (1.0 + hi)
+    k2 = lambda x, y, xp: xp.where(x < h, xp.zeros_like(x) + k2_left,
+                                   xp.zeros_like(x) + 0.5 * lam1)
+    return inputs.Problem(name="near_resonance", nx=2, ny=1, p=p, kappa=float(np.sqrt(k2_left)),
+                          domain=(0.0, 2 * h, 0.0, h), coef={"k2b": k2})
+
+
+def test_leaf_near_a_dirichlet_resonance(torch):
+    """The method's own edge case: A_ii nearly singular when kappa^2 b meets
+    a Dirichlet eigenvalue of the leaf.  FP64 meets the leaf's FP64 floor;
+    the FP32 factorisation cannot serve the left leaf (cond * 2^-24 > 1), so
+    the mixed path hands that leaf, and only that leaf, to the FP64 redo,
+    and both precisions then give S, X and u at the FP64 floor, with the
+    backward error of X at rounding level."""
+    from _common import backward_error, fp64_floor, p7_bar
+    prob = _near_resonant_problem()
+    bls = [oracle_leaf(prob, t) for t in range(2)]
+    conds = [float(np.linalg.cond(bl.Aii)) for bl, _ in bls]
+    _say(f"near resonance: cond(A_ii) = {conds[0]:.2e} (left), {conds[1]:.2e} (right)")
+    assert 1e7 <= conds[0] <= 1e9 and conds[1] < 1e4
+    B = _batch([prob])
+    nb, ni = 4 * (prob.p - 2), (prob.p - 2) ** 2
+    ub = torch.randn(B.nb_total, dtype=torch.float64, device="cuda")
+    flags = torch.empty(2, dtype=torch.int32, device="cuda")
+    for prec in (hps.HPS_FP64, hps.HPS_FP32_REFINE):
+        S, w, info, st = B.condense(prec=prec, max_refine=4, sync=True)
+        assert st == hps.HPS_OK and bool((info == 0).all())
+        hps.hps_batch_redo_flags(B.batch, flags)
+        Xt, _ = B.export()
+        ui = B.recover(ub, sync=True).view(2, ni).cpu().numpy()
+        fl = flags.cpu().numpy().tolist()
+        _say(f"  prec={prec}: redo flags {fl}")
+        if prec == hps.HPS_FP32_REFINE:
+            assert fl == [1, 0]
+        Sg = S.view(2, nb, nb).cpu().numpy()
+        Xg = Xt.view(2, nb, ni).cpu().numpy()
+        ubh = ub.view(2, nb).cpu().numpy()
+        for t, (bl, c) in enumerate(bls):
+            tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+            bar = max(tol, fp64_floor(bl.Aii))
+            eS, eX = relerr(Sg[t], c.S), relerr(Xg[t].T, c.X)
+            eu = relerr(ui[t], lf.recover(c, ubh[t]))
+            be = backward_error(bl.Aii, bl.Aib, Xg[t].T)
+            _say(f"    leaf {t}: S {eS:.1e} X {eX:.1e} u {eu:.1e} (bar {bar:.1e}), "
+                 f"backward {be:.1e}")
+            assert eS <= bar and eX <= bar and eu <= bar, t
+            assert be <= p7_bar(ni), t
+    B.close()

@@ -37,3 +37,16 @@ def test_cache_round_trip(tmp_path):
     tune.save_cache(path, {"p16_fp64_L4096": {"setting": [2, 64], "ms": 5.0}})
     assert os.path.exists(path)
     assert tune.load_cache(path)["p16_fp64_L4096"]["setting"] == [2, 64]
+
+
+def test_tuning_problem_keeps_the_leaf_boxes():
+    """The tuning sub-problem is the leading rows of the real leaves: same
+    boxes, hence the same conditioning and refinement behaviour."""
+    from paper_2211_14969_amd import inputs
+    import numpy as np
+    for prob in (inputs.uneven_batch()[1], inputs.multi_bump()):
+        sub = tune.tuning_problem(prob, 1024)
+        assert sub.nleaf <= 1024 and sub.nx == prob.nx
+        np.testing.assert_allclose(sub.boxes(), prob.boxes()[:sub.nleaf], rtol=0, atol=1e-15)
+    small = inputs.tiny()
+    assert tune.tuning_problem(small, 1024) is small
