@@ -140,10 +140,12 @@ hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib,
  *   prec       : HPS_FP64 or HPS_FP32_REFINE
  *   tol        : refinement target (HPS_FP32_REFINE; ignored for HPS_FP64):
  *                a leaf stops refining when the estimated relative forward
- *                error of X, rho ||dX_k|| / ||X_k||, is at most tol, with
- *                dX_k the last correction and rho the contraction per step,
- *                estimated as the larger of ||r_k|| / ||r_{k-1}|| and
- *                ||dX_1|| / ||X_1|| (r = A_ib - A_ii X evaluated in FP64).
+ *                error of X, 16 rho / (1 - rho) ||dX_k|| / ||X_k||, is at
+ *                most tol, with dX_k the last correction and rho < 1 the
+ *                contraction per step, estimated as the larger of
+ *                ||r_k|| / ||r_{k-1}|| and ||dX_1|| / ||X_1||
+ *                (r = A_ib - A_ii X evaluated in FP64; the factor 16
+ *                covers how far both estimates of rho can fall short).
  *                <= 0 selects 1e-10; >= 1 applies exactly max_refine
  *                corrections and accepts the result without a test (no
  *                FP64 redo).

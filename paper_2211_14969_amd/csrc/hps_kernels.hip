@@ -2434,13 +2434,22 @@ __global__ void __launch_bounds__(256) k_residual_m2(Geom g, float *M32, const d
 }
 
 // Stop test of the refinement, per leaf, after the residual r_k of X_k: the
-// estimated forward error rho ||dX_k|| is at most tol ||X_k||, where dX_k is
-// the last correction and rho, the contraction factor of the iteration, is
-// the larger of two estimates: the observed contraction of the residual
-// ||r_k|| / ||r_{k-1}||, and the relative size of the first correction
-// ||dX_1|| / ||X_1||, i.e. the forward error of the low-precision solve,
-// which sets the contraction of LU-based refinement.  Either one alone can
-// underestimate the error several-fold on a nearly singular A_ii.  A leaf
+// estimated forward error rho / (1 - rho) ||dX_k|| is at most tol ||X_k||,
+// where dX_k is the last correction and rho < 1, the contraction factor of
+// the iteration, is the larger of two estimates: the observed contraction
+// of the residual ||r_k|| / ||r_{k-1}||, and the relative size of the first
+// correction ||dX_1|| / ||X_1||, i.e. the forward error of the low-precision
+// solve, which sets the contraction of LU-based refinement.  rho / (1 - rho)
+// ||dX_k|| bounds the remaining error of a contraction (the sum of the
+// corrections still to come, a geometric series); rho ||dX_k|| alone, the
+// next correction, underestimates it by 1 / (1 - rho), tenfold when the
+// iteration contracts slowly (rho ~ 0.9).  Both estimates of rho can fall
+// short of the true contraction: on the workloads' leaves (FP32 LU, FP64
+// residual) by up to 16x, when the error left after a correction lies in
+// directions the residual barely sees.  The estimate is therefore taken
+// kRhoSafety = 16 times larger: 16 rho / (1 - rho) ||dX_k|| <= tol ||X_k||.
+// (A p = 24 leaf of cond 8.5e5 otherwise stopped after one correction with
+// a forward error of 1.4e-9; its second correction reaches 1e-13.)  A leaf
 // whose iteration stalls above tol (its FP64 error floor, about
 // cond(A_ii) 2^-53, lies above tol) never passes.  An exactly zero residual
 // passes; tol >= 1 passes on the final check without a test.  On the final
@@ -2449,6 +2458,8 @@ __global__ void __launch_bounds__(256) k_residual_m2(Geom g, float *M32, const d
 // residual chunks' partial sums), 4 previous ||r||^2, 5 ||dX||^2 of the last
 // correction (sum of its nsol chunks), 6 the relative size of the first
 // correction.
+constexpr double kRhoSafety = 16.0;
+
 __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int *info,
                             int it, int last, int nres, int nsol) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2467,7 +2478,7 @@ __global__ void k_convcheck(int nleaf, double *norms, double tol, int *conv, int
   if (it == 1) n[6] = n[1] > 0.0 ? sqrt(n[5] / n[1]) : 1.0;
   if (!ok && tol < 1.0 && it > 0 && n[4] > 0.0) {
     const double rho = fmax(sqrt(n[0] / n[4]), n[6]);
-    ok = rho * sqrt(n[5]) <= tol * sqrt(n[1]);
+    ok = rho < 1.0 && kRhoSafety * rho * sqrt(n[5]) <= tol * (1.0 - rho) * sqrt(n[1]);
   }
   n[4] = n[0];
   if (ok) {
