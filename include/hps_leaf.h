@@ -73,6 +73,9 @@ typedef enum {
 /* Limits of this build. */
 #define HPS_P_MIN 4
 #define HPS_P_MAX 32
+/* Size of the device array that holds the pass scratch of
+ * hps_leaf_condense_noalloc (one copy per GPU, kept for the process). */
+#define HPS_NOALLOC_SCRATCH_BYTES (512ull << 20)
 
 /* One group of leaves sharing the order p (a whole problem, or one order
  * class of a multi-problem batch).
@@ -166,6 +169,24 @@ hps_status hps_leaf_operator(hps_batch *b, int g, double *Aii, double *Aib,
 hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol,
                              int max_refine, const double *f, double *S,
                              double *w, int *info, int flags);
+
+/* The same computation as hps_leaf_condense (same arguments, results equal
+ * up to rounding), for callers that cannot allocate device memory at call
+ * time (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): its pass scratch (LU work matrices, pivots, retire
+ * steps and refinement bookkeeping) lives in a device array of
+ * HPS_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, instead of in
+ * the batch; it calls no allocating routine.  Each order group is processed
+ * in passes of as many leaves as that array holds (at p = 32 in FP64, 67
+ * leaves per pass), all on the context stream.  Returns HPS_ERR_INVALID,
+ * with nothing enqueued, if a single leaf of some group does not fit the
+ * array.  Every call on one GPU shares that GPU's array and overwrites it:
+ * calls that overlap on one GPU (two streams, or two threads) race and must
+ * be serialised by the caller.  The batch's stored X, h, flags and per-leaf
+ * status are updated as by hps_leaf_condense.  Async unless HPS_SYNC. */
+hps_status hps_leaf_condense_noalloc(hps_batch *b, hps_precision prec, double tol,
+                                     int max_refine, const double *f, double *S,
+                                     double *w, int *info, int flags);
 
 /* Interior recovery (Sec. 3, after eq. (constant_coeff_helm)):
  *   ub : device [total leaves][nb]  boundary values

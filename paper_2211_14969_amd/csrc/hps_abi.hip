@@ -6,6 +6,8 @@
 // and per-lane pass scratch sized for the largest mode: FP64 with a body-load
 // column).  hps_leaf_condense and hps_leaf_recover never allocate or free, so
 // they may be captured in a HIP graph after the batch is built.
+// hps_leaf_condense_noalloc runs the same path with its pass scratch in a
+// file-scope device array instead of the batch's.
 //
 // Concurrency: the order groups of a batch are dealt to up to kMaxLanes
 // lanes (largest work first, each lane taking the next group while its sum
@@ -197,6 +199,37 @@ hps::Geom shift(const hps::Geom &g, int l0) {
   if (g.c2) s.c2 = g.c2 + pp * l0;
   if (g.k2b) s.k2b = g.k2b + pp * l0;
   return s;
+}
+
+// Lays a Scratch over `bytes` of device memory at `base` for passes of at
+// most `leaves` leaves of work matrices of `per` bytes and R rows.
+Scratch carve(void *base, size_t bytes, size_t leaves, size_t per, int R) {
+  Scratch s;
+  char *p = (char *)base;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    off = align_up(off, 256);
+    char *q = p + off;
+    off += n;
+    return q;
+  };
+  s.ws = take(leaves * per);
+  s.ws_bytes = leaves * per;
+  s.piv = (int *)take(sizeof(int) * leaves * R);
+  s.rstep = (int *)take(sizeof(int) * leaves * R);
+  s.pr_elems = leaves * R;
+  s.norms = (double *)take(sizeof(double) * hps::kNormStride * leaves);
+  s.conv = (int *)take(sizeof(int) * leaves);
+  s.list = (int *)take(sizeof(int) * leaves);
+  s.count = (int *)take(sizeof(int) * 2);
+  s.max_leaves = leaves;
+  if (off > bytes) return Scratch();   // does not fit: empty
+  return s;
+}
+
+size_t carve_bytes(size_t leaves, size_t per, int R) {
+  return leaves * per + 2 * sizeof(int) * leaves * R + sizeof(double) * hps::kNormStride * leaves +
+         2 * sizeof(int) * leaves + 2 * sizeof(int) + 8 * 256;
 }
 
 // Leaves per pass of group g for a condense / recover that needs `per`
@@ -420,6 +453,34 @@ hps_status condense_epilogue(hps_batch *b, int nref, const double *f, int *info,
   return HPS_OK;
 }
 
+// --- the no-allocation variant's scratch --------------------------------
+// The array itself is declared at file scope below the anonymous namespace;
+// each device's address of it is taken once (hipGetSymbolAddress) and only
+// that pointer is passed to kernels.
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+hps_status noalloc_scratch(int device, void **out);
+
+}  // namespace
+
+// Pass scratch of hps_leaf_condense_noalloc: one array per GPU the library
+// runs on (each device holds its own copy at its own address), kept until
+// the process ends.  Host code never uses this name as an address.
+static __device__ __align__(256) char scratch[HPS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+hps_status noalloc_scratch(int device, void **out) {
+  if (device < 0 || device >= kMaxDevices) return HPS_ERR_INVALID;
+  if (!g_scratch_ptr[device]) {
+    void *p = nullptr;
+    HPS_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return HPS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -444,6 +505,13 @@ hps_status hps_ctx_create(void *stream, hps_ctx **out) {
   if (!c) return HPS_ERR_OOM;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return HPS_ERR_HIP;
+  }
+  // the no-allocation entry point's scratch address, taken once per device
+  // at set-up with that device current
+  void *p = nullptr;
+  if (noalloc_scratch(c->device, &p) != HPS_OK) {
     delete c;
     return HPS_ERR_HIP;
   }
@@ -699,6 +767,39 @@ hps_status hps_leaf_condense(hps_batch *b, hps_precision prec, double tol, int m
     return HPS_OK;
   });
   if (st != HPS_OK) return st;
+  return condense_epilogue(b, a.nref, f, info, flags);
+}
+
+hps_status hps_leaf_condense_noalloc(hps_batch *b, hps_precision prec, double tol, int max_refine,
+                                     const double *f, double *S, double *w, int *info, int flags) {
+  hps_status st = check_condense_args(b, prec, max_refine, S, f);
+  if (st != HPS_OK) return st;
+  const bool fp32 = prec == HPS_FP32_REFINE;
+  // every group must fit at least one leaf per pass (its FP64 redo too)
+  for (const Group &G : b->groups) {
+    const hps::Geom g = make_geom(G, G.geom.nb + (f ? 1 : 0));
+    if (carve_bytes(1, work_bytes_per_leaf(g, false), g.R) > HPS_NOALLOC_SCRATCH_BYTES)
+      return HPS_ERR_INVALID;
+  }
+  void *base = nullptr;
+  st = noalloc_scratch(b->ctx->device, &base);
+  if (st != HPS_OK) return st;
+  const CondenseArgs a{fp32, tol, fp32 ? max_refine : 0, f, S, w};
+  st = condense_prologue(b);
+  if (st != HPS_OK) return st;
+  hipStream_t s = b->ctx->stream;
+  for (const Group &G : b->groups) {
+    // the largest pass of this group's precision that fits the array
+    const hps::Geom g = make_geom(G, G.geom.nb + (f ? 1 : 0));
+    const size_t per = work_bytes_per_leaf(g, fp32);
+    const size_t one = carve_bytes(1, per, g.R) - carve_bytes(0, per, g.R);
+    const size_t n = std::min<size_t>(
+        G.d.nleaf, (HPS_NOALLOC_SCRATCH_BYTES - carve_bytes(0, per, g.R)) / one);
+    const Scratch sc = carve(base, HPS_NOALLOC_SCRATCH_BYTES, n, per, g.R);
+    if (!sc.ws) return HPS_ERR_INVALID;
+    st = condense_group(b, G, sc, s, a);
+    if (st != HPS_OK) return st;
+  }
   return condense_epilogue(b, a.nref, f, info, flags);
 }
 

@@ -36,8 +36,10 @@ EXPORTED = (
     "hps_batch_nleaf", "hps_batch_group_dims", "hps_leaf_nodes", "hps_leaf_operator",
     "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
     "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times", "hps_batch_set_tuning",
-    "hps_batch_redo_flags", "hps_batch_lanes",
+    "hps_leaf_condense_noalloc", "hps_batch_redo_flags", "hps_batch_lanes",
 )
+
+HPS_NOALLOC_SCRATCH_BYTES = 512 << 20
 
 HPS_NPHASE = 8
 PHASES = ("unused", "factor", "backsolve", "refine_solve", "schur", "recover", "refine_residual",
@@ -98,6 +100,8 @@ def load(path: str = LIB_PATH):
     L.hps_leaf_operator.argtypes = [vp, i, vp, vp, vp, vp]
     L.hps_leaf_condense.restype = i
     L.hps_leaf_condense.argtypes = [vp, i, d, i, vp, vp, vp, vp, i]
+    L.hps_leaf_condense_noalloc.restype = i
+    L.hps_leaf_condense_noalloc.argtypes = [vp, i, d, i, vp, vp, vp, vp, i]
     L.hps_batch_redo_flags.restype = i
     L.hps_batch_redo_flags.argtypes = [vp, vp]
     L.hps_batch_lanes.restype = i
@@ -215,6 +219,14 @@ def hps_leaf_condense(batch: int, prec: int, tol: float, max_refine: int, f, S, 
                                   _ptr(_f64(f, "f")), _ptr(_f64(S, "S")), _ptr(_f64(w, "w")),
                                   _ptr(info), int(flags))
     return _check(st, "hps_leaf_condense", allow)
+
+
+def hps_leaf_condense_noalloc(batch: int, prec: int, tol: float, max_refine: int, f, S, w=None,
+                              info=None, flags: int = 0, allow=(HPS_OK,)) -> int:
+    st = load().hps_leaf_condense_noalloc(ctypes.c_void_p(batch), int(prec), float(tol),
+                                          int(max_refine), _ptr(_f64(f, "f")), _ptr(_f64(S, "S")),
+                                          _ptr(_f64(w, "w")), _ptr(info), int(flags))
+    return _check(st, "hps_leaf_condense_noalloc", allow)
 
 
 def hps_batch_redo_flags(batch: int, flags) -> None:

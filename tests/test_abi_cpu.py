@@ -61,6 +61,8 @@ def test_argument_validation_without_device(lib):
     assert lib.hps_batch_group_dims(None, 0, None, None, None, None) == hps.HPS_ERR_INVALID
     assert lib.hps_batch_nleaf(None) == -1
     assert lib.hps_batch_destroy(None) == hps.HPS_OK
+    assert lib.hps_leaf_condense_noalloc(None, 0, 0.0, 0, None, None, None, None, 0) == \
+        hps.HPS_ERR_INVALID
     assert lib.hps_batch_redo_flags(None, None) == hps.HPS_ERR_INVALID
     assert lib.hps_batch_lanes(None) == -1
 
