@@ -6,16 +6,22 @@ collocation operator on the device, factor A_ii, solve for X = A_ii^{-1} A_ib
 and form S = A_bb - A_bi X (plus the FP64 refinement of X in the mixed
 precision mode).  Inputs (leaf boxes, coefficient samples) are resident in
 HBM before the timed region; nothing is copied to or from the host inside it.
-For the uneven eight-problem batch the step is the replay of one condense
-captured in a HIP graph, after the autotuner has picked the factorisation
-variant per order.  Recovery u_i = h - X u_b is timed separately against the
-HBM roofline.
 
-Workload: the unit square split into 64 x 64 leaves of order p = 16,
-kappa = 100, b(x) = 1 - 0.5 exp(-|x - (0.5, 0.5)|^2 / 0.05), in FP64.  The
-same batch is also condensed in FP32 + FP64 refinement and compared against
-the FP64 result; the plain FP64 CPU oracle is timed on a bounded sample of
-the same leaves.
+Default workload: the precision study, the unit square split into 32 x 32
+leaves of order p = 32, kappa = 300, b(x) = 1 - 0.3 sum of eight Gaussian
+bumps (width 0.03, centres from seed 3).  The headline is FP64; the same
+batch is timed in FP32 + FP64 refinement beside it ("compare").  For the
+uneven eight-problem batch each precision is autotuned and its step is the
+replay of one condense captured in a HIP graph.
+
+Accuracy, reported with the timing: every leaf's S from the two precisions
+is compared on the device, and for the leaves where they differ most plus a
+seeded sample the relative errors of S, X and the recovered u_i = h - X u_b
+(from a seeded u_b) against the FP64 CPU oracle are stated for both
+precisions.  Recovery is timed separately against the HBM roofline.  The
+CPU oracle is timed on the host's cores on a bounded sample of the same
+leaves, in two schedules (a leaf-parallel process pool with one BLAS thread
+per process, and one process with threaded BLAS), the faster reported.
 
 Prints one JSON line.
 """
@@ -24,6 +30,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -43,6 +50,14 @@ MEASURED_TRAFFIC = {
     ("d795a6e2ac355df0", "bumps_32x32_p32", "fp64"): {
         "kernel": "k_factorP<double, 512, 2>",
         "fetch_bytes": 51446724.896 * 2.0 * 1024, "write_bytes": 93056184.031 * 1.0 * 1024},
+}
+
+WORKLOADS = {
+    "bumps": ("multi_bump", "32x32 leaves p=32 kappa=300, eight bumps (default)"),
+    "bump": ("single_bump", "64x64 leaves p=16 kappa=100, one bump"),
+    "annulus": ("annulus", "quarter annulus 128x16 leaves p=20 kappa=150"),
+    "uneven": ("uneven_batch", "eight problems p=8..32 in one batch"),
+    "tiny": ("tiny", "4x4 leaves p=8 kappa=10"),
 }
 
 
@@ -67,87 +82,232 @@ def algorithmic_flops(p: int):
             "total": factor + back + schur}
 
 
-def cpu_baseline(problem, seconds: float):
-    """Time the FP64 CPU oracle (operator build + LAPACK condensation) on
-    consecutive leaves of the workload until `seconds` have elapsed."""
-    import numpy as np
+def make_problems(workload: str):
+    from paper_2211_14969_amd import inputs
+    made = getattr(inputs, WORKLOADS[workload][0])()
+    return made if isinstance(made, list) else [made]
+
+
+# --------------------------------------------------------------------------
+# CPU baseline: the oracle on the host's cores
+# --------------------------------------------------------------------------
+def _pool_init():
+    """One BLAS thread per worker: set before numpy loads its BLAS, and
+    limited again once it is loaded (threadpoolctl only sees loaded
+    libraries)."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    import numpy  # noqa: F401
+    import scipy.linalg  # noqa: F401
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+
+
+def _oracle_leaves(args):
+    """Condense leaves `ts` of problem `gi` of `workload` with the oracle
+    (operator build + LAPACK condensation); returns the count."""
+    workload, gi, ts = args
     from oracle import leaf as lf
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
-    boxes = problem.boxes()
+    prob = make_problems(workload)[gi]
+    boxes = prob.boxes()
+    for t in ts:
+        coef = lf.sample_coefficients(prob, boxes[t], prob.p)
+        lf.condense(lf.blocks(boxes[t], prob.p, coef))
+    return len(ts)
+
+
+def cpu_baseline(workload: str, budget_s: float):
+    """The FP64 oracle on a bounded sample of the workload's leaves (the
+    first problem's, for a multi-problem batch), in two schedules, each
+    timed five times (median): a leaf-parallel process pool with one BLAS
+    thread per process, and one process with threaded BLAS.  The faster is
+    reported, with its name and the threads it used."""
+    import multiprocessing as mp
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    cores = min(16, len(os.sched_getaffinity(0)))     # the host share of one GPU
+    prob = make_problems(workload)[0]
+    rng = np.random.default_rng(7)
     t0 = time.perf_counter()
-    n = 0
-    while True:
-        box = boxes[n % problem.nleaf]
-        coef = lf.sample_coefficients(problem, box, problem.p)
-        lf.condense(lf.blocks(box, problem.p, coef))
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds and n >= 4:
-            break
-    return {"value": n / el, "unit": "leaves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} consecutive leaves of the same workload, {el:.1f} s, "
-                      f"operator build + LU condensation per leaf in numpy/LAPACK FP64",
-            "host_cpus": len(os.sched_getaffinity(0))}
+    _oracle_leaves((workload, 0, [0]))
+    per_leaf = time.perf_counter() - t0
+    res = {}
+    # (a) process pool, one BLAS thread per process; each run holds about
+    # budget/10 seconds of oracle work per process
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores, initializer=_pool_init) as pool:
+        t0 = time.perf_counter()
+        pool.map(_oracle_leaves, [(workload, 0, [0])] * cores)     # warm the workers
+        t1 = time.perf_counter()
+        pool.map(_oracle_leaves, [(workload, 0, [1 % prob.nleaf])] * cores)
+        per_leaf_1 = time.perf_counter() - t1          # one leaf per worker, in parallel
+        n_pool = max(cores, int(budget_s / 10.0 * cores / max(per_leaf_1, 1e-3)))
+        runs = []
+        for _ in range(5):
+            ts = rng.choice(prob.nleaf, size=n_pool, replace=n_pool > prob.nleaf).tolist()
+            chunks = [(workload, 0, ts[k::cores]) for k in range(cores)]
+            t0 = time.perf_counter()
+            n = sum(pool.map(_oracle_leaves, chunks))
+            runs.append(n / (time.perf_counter() - t0))
+            print(f"# cpu oracle, process pool: {runs[-1]:.1f} leaves/s", file=sys.stderr,
+                  flush=True)
+    res["process_pool"] = {"value": statistics.median(runs), "cores": cores,
+                           "leaves_per_run": n_pool, "runs": runs}
+    # (b) one process, threaded BLAS
+    n_thr = max(2, int(budget_s / 10.0 / per_leaf))
+    with threadpool_limits(limits=cores):
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        runs = []
+        for _ in range(5):
+            ts = rng.choice(prob.nleaf, size=n_thr, replace=n_thr > prob.nleaf).tolist()
+            t0 = time.perf_counter()
+            n = _oracle_leaves((workload, 0, ts))
+            runs.append(n / (time.perf_counter() - t0))
+            print(f"# cpu oracle, threaded BLAS: {runs[-1]:.1f} leaves/s", file=sys.stderr,
+                  flush=True)
+    res["threaded_blas"] = {"value": statistics.median(runs), "cores": threads,
+                            "leaves_per_run": n_thr, "runs": runs}
+    best = max(res, key=lambda k: res[k]["value"])
+    return {"value": res[best]["value"], "unit": "leaves/s", "cores": res[best]["cores"],
+            "kind": "oracle", "schedule": best,
+            "sample": f"median of 5 runs of {res[best]['leaves_per_run']} random leaves of "
+                      f"{prob.name} (p={prob.p}): operator build + LU condensation per leaf "
+                      f"in numpy/LAPACK FP64",
+            "schedules": {k: {kk: vv for kk, vv in v.items() if kk != "runs"}
+                          for k, v in res.items()},
+            "host_cpus_visible": len(os.sched_getaffinity(0))}
+
+
+# --------------------------------------------------------------------------
+# GPU timing
+# --------------------------------------------------------------------------
+def time_precision(B, prec, steps, warmup, max_refine, use_graph, use_tune, phases_on):
+    """Tune (optionally), warm up, optionally capture one condense in a HIP
+    graph, then time `steps` steps between HIP events on the library stream.
+    Returns (ms per step, sorted per-step ms, phase times or None, tuned)."""
+    import torch
+    from paper_2211_14969_amd import hps
+    S, w, info = B.alloc_outputs()
+    tuned = None
+    if use_tune:
+        from paper_2211_14969_amd import tune
+        res = tune.tune_batch(B, prec=prec, max_refine=max_refine, reps=1, cache_path=None)
+        tuned = {B.groups[g].p: list(r["setting"]) for g, r in res.items()}
+
+    def condense():
+        hps.hps_leaf_condense(B.batch, prec, 0.0, max_refine, None, S, w, info, 0)
+
+    for _ in range(max(warmup, 1)):
+        condense()
+    torch.cuda.synchronize()
+    step = condense
+    if use_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=torch.cuda.current_stream()):
+            condense()
+        torch.cuda.synchronize()
+        step = graph.replay
+        step()
+        torch.cuda.synchronize()
+    timing = phases_on and not use_graph
+    hps.hps_ctx_set_timing(B.ctx, timing)
+    hps.hps_ctx_phase_times(B.ctx)          # reset
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record()
+    for i in range(steps):
+        step()
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    phases = hps.hps_ctx_phase_times(B.ctx) if timing else None
+    hps.hps_ctx_set_timing(B.ctx, False)
+    assert int((info != 0).sum().item()) == 0, "a leaf reported a failure"
+    return ms, per, phases, tuned
+
+
+def accuracy(B, max_refine, nworst=2, nrand=2, seed=11):
+    """Both precisions on the same batch: the largest per-leaf S gap between
+    them over every leaf, and, for the leaves where it is largest plus a
+    seeded sample (per problem), the relative errors of S, X and u against
+    the FP64 oracle."""
+    import numpy as np
+    import torch
+    from oracle import leaf as lf
+    from paper_2211_14969_amd import hps
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests"))
+    from _common import oracle_leaf, relerr
+
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    ub = torch.randn(B.nb_total, generator=gen, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, prec in (("fp64", hps.HPS_FP64), ("fp32+refine", hps.HPS_FP32_REFINE)):
+        S, _, info, st = B.condense(prec=prec, max_refine=max_refine, sync=True)
+        Xt, _ = B.export()
+        u = B.recover(ub, sync=True)
+        out[name] = (S, Xt, u, hps.hps_batch_stats(B.batch)[1])
+    gap_max, checked = 0.0, 0
+    err = {k: {"S": 0.0, "X": 0.0, "u": 0.0} for k in out}
+    rng = np.random.default_rng(seed)
+    views = {k: (B.split(v[0], "S"), B.split(v[1], "Xt"), B.split(v[2], "ui"))
+             for k, v in out.items()}
+    ubs = B.split(ub, "ub")
+    for gi, G in enumerate(B.groups):
+        s64, s32 = views["fp64"][0][gi], views["fp32+refine"][0][gi]
+        gap = (s32 - s64).flatten(1).norm(dim=1) / s64.flatten(1).norm(dim=1)
+        gap_max = max(gap_max, gap.max().item())
+        leaves = set(torch.topk(gap, min(nworst, G.nleaf)).indices.tolist())
+        leaves.update(rng.choice(G.nleaf, size=min(nrand, G.nleaf), replace=False).tolist())
+        ubh = ubs[gi].cpu().numpy()
+        for t in sorted(leaves):
+            bl, c = oracle_leaf(G.problem, t)
+            u_or = lf.recover(c, ubh[t])
+            checked += 1
+            for k, (Sv, Xv, uv) in views.items():
+                e = err[k]
+                e["S"] = max(e["S"], relerr(Sv[gi][t].cpu().numpy(), c.S))
+                e["X"] = max(e["X"], relerr(Xv[gi][t].cpu().numpy().T, c.X))
+                e["u"] = max(e["u"], relerr(uv[gi][t].cpu().numpy(), u_or))
+    return {"leaves_checked_vs_oracle": checked,
+            "selection": f"per problem the {nworst} leaves with the largest FP32-vs-FP64 S gap "
+                         f"and {nrand} random (seed {seed})",
+            "max_relerr_vs_oracle": err,
+            "max_leaf_gap_S_fp32_vs_fp64_all_leaves": gap_max,
+            "leaves_redone_fp64": out["fp32+refine"][3]}
 
 
 def recover_timing(B, steps: int):
     """Time hps_leaf_recover (stored X) on the condensed batch: u_i = h - X u_b
-    per leaf.  HBM-bound: reads X (8 ni nb bytes per leaf) and u_b, writes u_i."""
+    per leaf.  HBM-bound: reads X (8 ni nb bytes per leaf) and u_b, writes u_i.
+    Also the paper's alternative (Remark in Sec. 2): re-form and re-factor
+    A_ii and solve for the one right-hand side f_i - A_ib u_b, nothing
+    stored."""
     import torch
     from paper_2211_14969_amd import hps
     ub = torch.randn(B.nb_total, dtype=torch.float64, device="cuda")
     ui = torch.empty(B.ni_total, dtype=torch.float64, device="cuda")
-    hps.hps_leaf_recover(B.batch, ub, None, ui, 0)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        hps.hps_leaf_recover(B.batch, ub, None, ui, 0)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    nbytes = sum(8.0 * G.nleaf * (G.ni * G.nb + G.nb + G.ni) for G in B.groups)
-    gbs = nbytes / (ms * 1e-3) / 1e9
-    # the paper's alternative (Remark in Sec. 2): re-form and re-factor A_ii
-    # and solve for the one right-hand side f_i - A_ib u_b, nothing stored
-    flags = hps.HPS_RECOVER_REFACTOR
-    hps.hps_leaf_recover(B.batch, ub, None, ui, flags)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
+    out = {}
+    for name, flags in (("stored_x", 0), ("refactor", hps.HPS_RECOVER_REFACTOR)):
         hps.hps_leaf_recover(B.batch, ub, None, ui, flags)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_rf = e0.elapsed_time(e1) / steps
-    return {"ms": ms, "leaves_per_s": B.nleaf / (ms * 1e-3), "bytes": nbytes, "GB_per_s": gbs,
-            "frac_hbm_peak": gbs / 8000.0, "bound": "hbm",
-            "refactor_mode": {"ms": ms_rf, "leaves_per_s": B.nleaf / (ms_rf * 1e-3),
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            hps.hps_leaf_recover(B.batch, ub, None, ui, flags)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+    nbytes = sum(8.0 * G.nleaf * (G.ni * G.nb + G.nb + G.ni) for G in B.groups)
+    gbs = nbytes / (out["stored_x"] * 1e-3) / 1e9
+    return {"ms": out["stored_x"], "leaves_per_s": B.nleaf / (out["stored_x"] * 1e-3),
+            "bytes": nbytes, "GB_per_s": gbs, "frac_hbm_peak": gbs / 8000.0, "bound": "hbm",
+            "refactor_mode": {"ms": out["refactor"],
+                              "leaves_per_s": B.nleaf / (out["refactor"] * 1e-3),
                               "precision": "fp64"}}
-
-
-def worst_leaf_floor(B, gi: int, t: int) -> dict:
-    """Order, cond_2(A_ii) and the FP64 floor 10 cond 2^-53 of leaf t of group
-    gi: two correct FP64 results for that leaf may differ by about that much
-    (rounding the operator entries alone moves X so far)."""
-    import numpy as np
-    import torch
-    from paper_2211_14969_amd import hps
-    G = B.groups[gi]
-    d = {"p": G.p, "box": G.box[t:t + 1].contiguous()}
-    for name, c in G.coef.items():
-        d[name] = c[t:t + 1].contiguous()
-    one = hps.hps_leaf_build(B.ctx, [d])
-    Aii = torch.empty((1, G.ni, G.ni), dtype=torch.float64, device="cuda")
-    hps.hps_leaf_operator(one, 0, Aii)
-    torch.cuda.synchronize()
-    hps.hps_batch_destroy(one)
-    cond = float(np.linalg.cond(Aii[0].cpu().numpy()))
-    return {"p": G.p, "leaf": t, "cond_Aii": cond, "fp64_floor": 10.0 * cond * 2.0 ** -53}
 
 
 def main() -> int:
@@ -155,20 +315,19 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", choices=("fp64", "fp32"), default=None,
-                    help="precision of the timed path (fp32 = FP32 + FP64 refinement); "
-                         "default fp64, fp32 for the uneven batch")
+    ap.add_argument("--prec", choices=("fp64", "fp32"), default="fp64",
+                    help="precision of the headline (fp32 = FP32 + FP64 refinement)")
     ap.add_argument("--max-refine", type=int, default=4)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="approximate CPU time budget of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
-                    help="skip the run of the other precision on the same batch")
+                    help="skip the timing of the other precision")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the accuracy check against the oracle")
     ap.add_argument("--no-recover", action="store_true", help="skip the recovery timing")
-    ap.add_argument("--workload", default="bump",
-                    choices=("bump", "tiny", "bumps", "annulus", "uneven"),
-                    help="bump: 64x64 leaves p=16 (default, the headline configuration); "
-                         "tiny: 4x4 p=8; bumps: 32x32 p=32; annulus: 128x16 p=20; "
-                         "uneven: the eight-problem batch p=8..32 in one batch")
+    ap.add_argument("--workload", default="bumps", choices=tuple(WORKLOADS),
+                    help="; ".join(f"{k}: {v[1]}" for k, v in WORKLOADS.items()))
     ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
                     help="time replays of one condense captured in a HIP graph "
                          "(auto: on for the uneven batch)")
@@ -186,7 +345,7 @@ def main() -> int:
         return 2
 
     import torch
-    from paper_2211_14969_amd import hps, inputs
+    from paper_2211_14969_amd import hps
     from paper_2211_14969_amd.harness import LeafBatch
 
     if not torch.cuda.is_available():
@@ -203,67 +362,28 @@ def main() -> int:
         return 0
     hps.load()
     uneven = args.workload == "uneven"
-    prec_name = args.prec or ("fp32" if uneven else "fp64")
     use_graph = args.graph == "on" or (args.graph == "auto" and uneven)
     use_tune = args.tune == "on" or (args.tune == "auto" and uneven)
-    if use_graph:
-        # capture needs a stream other than the legacy default one; the
-        # library context binds to the current stream when the batch is built
-        torch.cuda.set_stream(torch.cuda.Stream())
-    probs = {"bump": lambda: [inputs.single_bump()], "tiny": lambda: [inputs.tiny()],
-             "bumps": lambda: [inputs.multi_bump()], "annulus": lambda: [inputs.annulus()],
-             "uneven": lambda: inputs.uneven_batch()}[args.workload]()
+    # graph capture needs a stream other than the legacy default one; the
+    # library context binds to the current stream when the batch is built
+    torch.cuda.set_stream(torch.cuda.Stream())
+    probs = make_problems(args.workload)
     prob = probs[0]
-    p, L = prob.p, sum(q.nleaf for q in probs)
+    L = sum(q.nleaf for q in probs)
     print(f"# workload {args.workload}: {L} leaves, p={[q.p for q in probs]}", file=sys.stderr,
           flush=True)
     B = LeafBatch(probs)
-    S, w, info = B.alloc_outputs()
+    prec_name = args.prec
     prec = hps.HPS_FP64 if prec_name == "fp64" else hps.HPS_FP32_REFINE
-    tuned = None
-    if use_tune:
-        from paper_2211_14969_amd import tune
-        tuned = tune.tune_batch(B, prec=prec, max_refine=args.max_refine, reps=1, cache_path=None)
-        tuned = {B.groups[g].p: list(r["setting"]) for g, r in tuned.items()}
-        print(f"# tuned (variant, chunk) per order: {tuned}", file=sys.stderr, flush=True)
-
-    def condense(pr=prec, S_=S):
-        hps.hps_leaf_condense(B.batch, pr, 0.0, args.max_refine, None, S_, w, info, 0)
-
-    for _ in range(max(args.warmup, 1)):
-        condense()
-    torch.cuda.synchronize()
-    st = hps.hps_leaf_condense(B.batch, prec, 0.0, args.max_refine, None, S, w, info, hps.HPS_SYNC)
-    print(f"# warmup done, status {st}", file=sys.stderr, flush=True)
-    step = condense
-    if use_graph:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph, stream=torch.cuda.current_stream()):
-            condense()
-        torch.cuda.synchronize()
-        step = graph.replay
-
-    hps.hps_ctx_set_timing(B.ctx, not use_graph)
-    hps.hps_ctx_phase_times(B.ctx)          # reset
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    evs[0].record()
-    for i in range(args.steps):
-        step()
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    per = sorted(evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps))
-    ms = evs[0].elapsed_time(evs[-1]) / args.steps
-    phases = hps.hps_ctx_phase_times(B.ctx)
-    hps.hps_ctx_set_timing(B.ctx, False)
-    bad = int((info != 0).sum().item())
+    ms, per, phases, tuned = time_precision(B, prec, args.steps, args.warmup, args.max_refine,
+                                            use_graph, use_tune, phases_on=True)
     redo = hps.hps_batch_stats(B.batch)[1]
+    print(f"# timed {prec_name}: {ms:.3f} ms per step", file=sys.stderr, flush=True)
 
     fl = {k: sum(algorithmic_flops(q.p)[k] * q.nleaf for q in probs) / L
           for k in ("factor", "backsolve", "schur", "total")}
-    dtype = "f64" if prec_name == "fp64" else "f32+f64"
-    peak = PEAK_TFLOPS["fp64"]
     value = L / (ms * 1e-3)
+    workload_name = prob.name if len(probs) == 1 else "uneven_8_problems"
     line = {
         "metric": "leaf condensations/s + % MFMA peak; FP64 vs FP32+refine at <=1e-9 rel err",
         "value": value,
@@ -277,31 +397,31 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": "f64" if prec_name == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": prob.name if len(probs) == 1 else "uneven_8_problems",
-                   "leaves": L, "p": p if len(probs) == 1 else [q.p for q in probs],
+        "config": {"workload": workload_name,
+                   "leaves": L, "p": prob.p if len(probs) == 1 else [q.p for q in probs],
                    "kappa": prob.kappa if len(probs) == 1 else [q.kappa for q in probs],
                    "b": prob.meta.get("b"), "precision": prec_name, "max_refine": args.max_refine,
-                   "graph_replay": use_graph, "tuned": tuned, "parallelism": "single-gpu"},
+                   "graph_replay": use_graph, "tuned": tuned,
+                   "lanes": hps.hps_batch_lanes(B.batch), "parallelism": "single-gpu"},
         "useful_tflops": fl["total"] * L / (ms * 1e-3) / 1e12,
         "useful_frac_fp64_peak": fl["total"] * L / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
-        "leaves_with_nonzero_info": bad,
         "leaves_redone_fp64": redo,
     }
-    if not use_graph:
+    if phases is not None:
         f_ms, f_n = phases["factor"]
-        t_factor = f_ms / args.steps          # ms of factorisation launches per step
-        achieved = fl["factor"] * L / (t_factor * 1e-3) / 1e12
+        achieved = fl["factor"] * L * args.steps / (f_ms * 1e-3) / 1e12
         line["phases_ms_per_step"] = {k: v[0] / args.steps for k, v in phases.items() if v[1]}
-        # every tile product runs on the FP64 MFMA in both precisions
         line["roofline"] = {"bound": "mfma", "kernel": "factorisation", "achieved": achieved,
-                            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                            "traffic": None,
+                            "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                            "frac": achieved / PEAK_TFLOPS["fp64"], "traffic": None,
                             "per_launch_flop": fl["factor"] * L * args.steps / max(f_n, 1),
                             "launch_ms": f_ms / max(f_n, 1),
-                            "launches_per_step": f_n / args.steps}
-        tr = MEASURED_TRAFFIC.get((kernel_source_hash(), line["config"]["workload"], prec_name))
+                            "launches_per_step": f_n / args.steps,
+                            "timing": "HIP events around each launch on the library stream, "
+                                      "inside the timed region"}
+        tr = MEASURED_TRAFFIC.get((kernel_source_hash(), workload_name, prec_name))
         if tr is not None:
             line["roofline"]["kernel"] = tr["kernel"]
             line["roofline"]["traffic"] = tr["fetch_bytes"] + tr["write_bytes"]
@@ -310,45 +430,32 @@ def main() -> int:
 
     if not args.no_compare:
         other = hps.HPS_FP32_REFINE if prec == hps.HPS_FP64 else hps.HPS_FP64
-        S2 = torch.empty_like(S)
-        for _ in range(2):
-            condense(other, S2)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        n2 = max(3, args.steps // 2)
-        e0.record()
-        for _ in range(n2):
-            condense(other, S2)
-        e1.record()
-        torch.cuda.synchronize()
-        ms2 = e0.elapsed_time(e1) / n2
-        rel, worst, above = 0.0, (0, 0), 0
-        for gi, (Sa, Sb) in enumerate(zip(B.split(S, "S"), B.split(S2, "S"))):
-            r = (Sa - Sb).flatten(1).norm(dim=1) / Sb.flatten(1).norm(dim=1)
-            above += int((r > 1e-9).sum().item())
-            m, t = r.max(dim=0)
-            if m.item() > rel:
-                rel, worst = m.item(), (gi, int(t.item()))
-        redo2 = hps.hps_batch_stats(B.batch)[1]
-        line["compare"] = {"precision": "fp32+refine" if other == hps.HPS_FP32_REFINE else "fp64",
-                           "leaves_redone_fp64": redo2,
-                           "leaves_per_s": L / (ms2 * 1e-3), "ms_per_step": ms2,
-                           "eager": True,
-                           "max_leaf_relerr_S_vs_other": rel,
-                           "leaves_above_1e-9": above,
-                           "worst_leaf": worst_leaf_floor(B, *worst)}
-        condense()               # leave the timed precision's X in the batch
-        torch.cuda.synchronize()
+        ms2, per2, ph2, tuned2 = time_precision(B, other, max(5, args.steps // 2), 2,
+                                                args.max_refine, use_graph, use_tune,
+                                                phases_on=True)
+        cmp_ = {"precision": "fp32+refine" if other == hps.HPS_FP32_REFINE else "fp64",
+                "leaves_per_s": L / (ms2 * 1e-3), "ms_per_step": ms2,
+                "ms_per_step_median": per2[len(per2) // 2], "graph_replay": use_graph,
+                "tuned": tuned2, "leaves_redone_fp64": hps.hps_batch_stats(B.batch)[1],
+                "speedup_vs_headline": ms / ms2}
+        if ph2 is not None:
+            cmp_["phases_ms_per_step"] = {k: v[0] / len(per2) for k, v in ph2.items() if v[1]}
+        line["compare"] = cmp_
+        print(f"# timed the other precision: {ms2:.3f} ms per step", file=sys.stderr, flush=True)
+
+    if not args.no_accuracy:
+        line["accuracy"] = accuracy(B, args.max_refine)
+        print("# accuracy checked", file=sys.stderr, flush=True)
 
     if not args.no_recover:
+        B.condense(prec=prec, max_refine=args.max_refine, sync=True)
         line["recover"] = recover_timing(B, max(3, args.steps // 2))
 
     if not args.no_cpu:
         print("# timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
         if len(probs) > 1:
-            line["cpu_baseline"]["sample"] += f" (first problem, p={prob.p})"
+            line["cpu_baseline"]["sample"] += " (first problem of the batch)"
     B.close()
     print(json.dumps(line), flush=True)
     return 0
