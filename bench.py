@@ -41,15 +41,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # 1.0 against a 1 GiB device copy), keyed by the sha256 prefix of the kernel
 # source it was measured on, the workload and the precision.
 MEASURED_TRAFFIC = {
-    ("d795a6e2ac355df0", "bump_64x64_p16", "fp64"): {
-        "kernel": "k_factor2_t<double, 2>",
-        "fetch_bytes": 3003746.896 * 2.0 * 1024, "write_bytes": 8168543.906 * 1.0 * 1024},
-    ("d795a6e2ac355df0", "bump_64x64_p16", "fp32"): {
-        "kernel": "k_factor2_t<float, 3>",
-        "fetch_bytes": 1477504.146 * 2.0 * 1024, "write_bytes": 4122125.177 * 1.0 * 1024},
-    ("d795a6e2ac355df0", "bumps_32x32_p32", "fp64"): {
-        "kernel": "k_factorP<double, 512, 2>",
-        "fetch_bytes": 51446724.896 * 2.0 * 1024, "write_bytes": 93056184.031 * 1.0 * 1024},
+    ("41d1c930185dd331", "bumps_32x32_p32", "fp64"): {
+        "kernel": "k_factor_ll<double, 8, 8, 2, 2, 1>",
+        "fetch_bytes": 39800223.479 * 2.0 * 1024, "write_bytes": 8330976.349 * 1.0 * 1024},
 }
 
 WORKLOADS = {
@@ -333,6 +327,11 @@ def main() -> int:
                          "(auto: on for the uneven batch)")
     ap.add_argument("--tune", choices=("auto", "on", "off"), default="auto",
                     help="autotune every order group before timing (auto: on for the uneven batch)")
+    ap.add_argument("--factor-variant", type=int, default=None,
+                    help="force the factorisation variant of every order group "
+                         "(hps_batch_set_tuning; default: the library's choice or the tuner's)")
+    ap.add_argument("--factor-chunk", type=int, default=0,
+                    help="tuning chunk passed with --factor-variant")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times "
                          "(calibrates the HBM traffic counters against a known byte count)")
@@ -373,6 +372,9 @@ def main() -> int:
     print(f"# workload {args.workload}: {L} leaves, p={[q.p for q in probs]}", file=sys.stderr,
           flush=True)
     B = LeafBatch(probs)
+    if args.factor_variant is not None:
+        for gi in range(len(B.groups)):
+            hps.hps_batch_set_tuning(B.batch, gi, args.factor_variant, args.factor_chunk)
     prec_name = args.prec
     prec = hps.HPS_FP64 if prec_name == "fp64" else hps.HPS_FP32_REFINE
     ms, per, phases, tuned = time_precision(B, prec, args.steps, args.warmup, args.max_refine,
@@ -404,6 +406,7 @@ def main() -> int:
                    "kappa": prob.kappa if len(probs) == 1 else [q.kappa for q in probs],
                    "b": prob.meta.get("b"), "precision": prec_name, "max_refine": args.max_refine,
                    "graph_replay": use_graph, "tuned": tuned,
+                   "factor_variant": args.factor_variant, "factor_chunk": args.factor_chunk,
                    "lanes": hps.hps_batch_lanes(B.batch), "parallelism": "single-gpu"},
         "useful_tflops": fl["total"] * L / (ms * 1e-3) / 1e12,
         "useful_frac_fp64_peak": fl["total"] * L / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],

@@ -203,13 +203,20 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
 
 /* Tuning of group g's factorisation (for an autotuner; the defaults are
  * chosen automatically):
- *   factor_variant : 0 automatic, 1 one 16-column panel per trailing pass,
+ *   factor_variant : 0 automatic, 4 left-looking: each 32-column block
+ *                    column held in registers, formed from the operator,
+ *                    updated by the earlier panels (multipliers read, never
+ *                    rewritten) with rows kept in pivot order, then its own
+ *                    panels factored (chunk_cols 64 / 128: four / eight row
+ *                    tiles per wavefront loaded a step ahead, else two),
+ *                    1 one 16-column panel per trailing pass,
  *                    2 panels in pairs (one trailing pass per 32 columns;
  *                    both panels in LDS when (p-2)^2 <= 256 (FP64: < 256),
  *                    else the first panel's multipliers re-read from the
  *                    work matrix), 3 the whole work matrix held in registers
  *                    (HPS_FP32_REFINE and p <= 16 only; elsewhere the
- *                    automatic choice).  Automatic is 2, except 1 for
+ *                    automatic choice).  Automatic is 4 for HPS_FP64 above
+ *                    400 rows (p >= 23), else 2, except 1 for
  *                    HPS_FP32_REFINE when 256 < (p-2)^2 < 400.
  *   chunk_cols     : 0 automatic, else the column width (multiple of 16, at
  *                    most 1024) of the U12 / trailing passes; ignored when

@@ -155,7 +155,7 @@ struct hps_batch {
 namespace {
 
 size_t work_bytes_per_leaf(const hps::Geom &g, bool fp32) {
-  return (size_t)g.RT * g.CT * 256 * (fp32 ? 4 : 8);
+  return hps::leaf_tiles(g) * 256 * (fp32 ? 4 : 8);
 }
 
 hps::Geom make_geom(const hps_leaf_desc &d, const double *dtab, int nrhs) {
@@ -168,6 +168,7 @@ hps::Geom make_geom(const hps_leaf_desc &d, const double *dtab, int nrhs) {
   g.RT = g.R / 16;
   g.nrhs = nrhs;
   g.CT = g.RT + (nrhs + 15) / 16;
+  g.mdiv = (65536 + g.m - 1) / g.m;
   g.box = d.box;
   g.a11 = d.a11;
   g.a22 = d.a22;
@@ -833,7 +834,7 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f, dou
 
 hps_status hps_batch_set_tuning(hps_batch *b, int g, int factor_variant, int chunk_cols) {
   if (!b || g < 0 || g >= (int)b->groups.size()) return HPS_ERR_INVALID;
-  if (factor_variant < 0 || factor_variant > 3) return HPS_ERR_INVALID;
+  if (factor_variant < 0 || factor_variant > 4) return HPS_ERR_INVALID;
   if (chunk_cols < 0 || chunk_cols > 1024 || (chunk_cols & 15)) return HPS_ERR_INVALID;
   b->groups[g].tune_variant = factor_variant;
   b->groups[g].tune_ch = chunk_cols;

@@ -16,6 +16,7 @@ struct Geom {
   int R;        // ni rounded up to 16: rows / A-part columns of the work matrix
   int RT;       // R / 16 row tiles
   int CT;       // column tiles of the work matrix (A part + right-hand sides)
+  int mdiv;     // ceil(2^16 / m): n / m == (n * mdiv) >> 16 for 0 <= n < 2048
   int nrhs;     // right-hand-side columns in use
   const double *box;                        // [nleaf][4]
   const double *a11, *a22, *c1, *c2, *k2b;  // [nleaf][p*p] or nullptr
@@ -25,6 +26,12 @@ struct Geom {
                       // 3 register-resident (FP32, R <= 208)
   int tune_ch;        // column chunk of the U12 / trailing passes (0 automatic)
 };
+
+// 16 x 16 tiles of one leaf's slot in the factorisation workspace: the work
+// matrix (RT x CT tiles) and one tile per panel for its L11^{-1}.
+__host__ __device__ inline size_t leaf_tiles(const Geom &g) {
+  return (size_t)g.RT * (g.CT + 1);
+}
 
 // Right-hand-side layouts of the work matrix.
 enum RhsMode : int {

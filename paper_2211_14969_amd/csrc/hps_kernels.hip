@@ -123,8 +123,14 @@ __device__ __forceinline__ bool resolve_leaf(const Sel &sel, int &leaf) {
   return true;
 }
 
-__device__ __forceinline__ size_t leaf_stride(const Geom &g) {
+// Elements of a leaf's work matrix W, and of its slot in the workspace: W
+// followed by one 16 x 16 tile per panel (the left-looking factorisation
+// keeps each panel's L11^{-1} there).
+__device__ __forceinline__ size_t work_elems(const Geom &g) {
   return (size_t)g.RT * g.CT * 256;
+}
+__device__ __forceinline__ size_t leaf_stride(const Geom &g) {
+  return (size_t)leaf_tiles(g) * 256;
 }
 
 // Boundary slot b -> grid node (k, l):  W, E, S, N, each p-2 nodes.
@@ -194,8 +200,14 @@ __device__ __forceinline__ double build_elem(const Geom &g, LeafScale sc, int le
   const int p = g.p, m = g.m, ni = g.ni, nb = g.nb, R = g.R;
   if (r >= ni) return (c == r) ? 1.0 : 0.0;
   const size_t nbase = (size_t)leaf * p * p;
-  const int i = r % m + 1, j = r / m + 1;
-  if (c < ni) return opval(g, g.D, g.D2, sc, nbase, i, j, c % m + 1, c / m + 1);
+  const int jr0 = (r * g.mdiv) >> 16;           // r / m (exact for r < 2048)
+  const int i = r - jr0 * m + 1, j = jr0 + 1;
+  if (c < ni) {
+    const int lc0 = (c * g.mdiv) >> 16;
+    const int k = c - lc0 * m + 1, l = lc0 + 1;
+    if (k != i && l != j) return 0.0;            // not on the row's grid lines
+    return opval(g, g.D, g.D2, sc, nbase, i, j, k, l);
+  }
   if (c < R) return 0.0;
   const int jr = c - R;
   if (bs.mode == RHS_CONDENSE) {
@@ -416,7 +428,7 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
   // form W from the operator (coalesced, tile-major); the leaf's matrix is
   // read back by this workgroup right away, mostly from cache
   {
-    const size_t total = leaf_stride(g);
+    const size_t total = work_elems(g);
     for (size_t e = tid; e < total; e += NT) {
       const int tile = (int)(e >> 8);
       int ri, ci;
@@ -677,7 +689,7 @@ __global__ void __launch_bounds__(256, MINB) k_factor2_t(Geom g, T *M, int *piv,
   for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
   if (tid == 0) *zeroPiv = 0;
   {
-    const size_t total = leaf_stride(g);
+    const size_t total = work_elems(g);
     for (size_t e = tid; e < total; e += NT) {
       const int tile = (int)(e >> 8);
       int ri, ci;
@@ -898,7 +910,7 @@ __global__ void __launch_bounds__(NT, MINW) k_factorP(Geom g, T *M, int *piv, in
   for (int r = tid; r < R; r += NT) rst[r] = kInfoActive;
   if (tid == 0) *zeroPiv = 0;
   {
-    const size_t total = leaf_stride(g);
+    const size_t total = work_elems(g);
     for (size_t e = tid; e < total; e += NT) {
       const int tile = (int)(e >> 8);
       int ri, ci;
@@ -1181,6 +1193,398 @@ __device__ __forceinline__ void rr_panel_columns(float (&v)[4][16], unsigned &ac
                                                  float *prb, int *pv, int *rst, int &zp,
                                                  std::integer_sequence<int, Cs...>) {
   (rr_panel_column<Cs>(v, act, lane, k, prb, pv, rst, zp), ...);
+}
+
+// Workgroup barrier ordering LDS accesses only: global loads still in flight
+// (the next step's prefetched operands) are not waited for, as they would be
+// by __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// ---------------------------------------------------------------------------
+// factor_ll: left-looking blocked LU with partial pivoting, one workgroup
+// per leaf, one block column of KT column tiles (16 KT columns) at a time
+// held in the accumulator registers of the workgroup: wavefront w owns the
+// row tiles w, w + NW, ... of the block column.
+//
+// The rows are kept in their pivot order ("positions"): after block column
+// J the pivots of its panels take the positions 16 k ... 16 k + 15 (panel
+// k, pivot order), the rows they displace take the pivots' old positions,
+// and later block columns are formed with their rows in that order.  So
+// when a block column takes the update of an earlier panel j, the rows that
+// need it are exactly the positions from 16 (j + 1) on (no padding work on
+// rows retired earlier), and the update is
+//   U_j = L11_j^{-1} (rows 16 j ... 16 j + 15 of the block column)
+//   rows from 16 (j + 1) on:  -= L21_j U_j
+// with L21_j read from the work matrix (rows gathered through the position
+// table) and L11_j^{-1} stored per panel beside the work matrix.  Each
+// block column is formed from the operator directly (never read back), the
+// earlier multipliers are read but never rewritten, and the block column is
+// written once.  Its own panels are then factored: each panel goes to LDS,
+// is eliminated with partial pivoting over the positions not yet retired
+// (the largest magnitude, ties to the lowest position), and updates the
+// block column's later tiles.  The result is the stored form of k_factor
+// (multipliers in the panel columns, U rows in the pivot rows, pivot lists
+// and retire steps, all indexed by the original rows), so the solves read
+// it unchanged; the right-hand-side columns are block columns too, so the
+// forward elimination happens on the way.
+// ---------------------------------------------------------------------------
+template <typename T, int NW, int RTW, int KT, int PF, int MINB>
+__global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *piv, int *rstep,
+                                                            int *info, Sel sel, BuildSrc bs) {
+  constexpr int NT = 64 * NW;
+  constexpr int KW = 16 * KT;
+  using Acc = typename Mfma<T>::acc;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  const int R = g.R, RT = g.RT, CT = g.CT;
+  T *P = (T *)smem;                          // [R][kPST]  panel, rows = positions - 16 c0
+  T *Ub = P + (size_t)R * kPST;              // [2][16][KW] U rows
+  T *Lk = Ub + 2 * 16 * KW;                  // [16][kPST] L11^{-1} of the current panel
+  T *redv = Lk + 16 * kPST;                  // [NW]
+  int *ord = (int *)(redv + NW);             // [R] position -> row
+  int *where = ord + R;                      // [R] row -> position
+  int *pst = where + R;                      // [R] (position - 16 c0) -> panel that retired it
+  int *prow = pst + R;                       // [R] (position - 16 c0) -> index in its panel's pivots
+  int *pvs = prow + R;                       // [KT][16] pivots of this block column's panels
+  int *redi = pvs + 16 * KT;                 // [NW]
+  int *zeroPiv = redi + NW;                  // [1]
+  T *Ml = M + leaf_stride(g) * wi;
+  T *Lg = Ml + work_elems(g);                // [RT][16][16] L11^{-1} of every panel
+  const LeafScale sc = leaf_scale(g, leaf);
+  const int lr = lane >> 4, lc = lane & 15;
+
+  for (int r = tid; r < R; r += NT) {
+    ord[r] = r;
+    where[r] = r;
+  }
+  if (tid == 0) *zeroPiv = 0;
+  __syncthreads();
+
+  Acc acc[RTW][KT];
+  const int nblk = (CT + KT - 1) / KT;
+  for (int J = 0; J < nblk; ++J) {
+    const int c0 = J * KT;
+    const int ncol = min(KT, CT - c0);          // column tiles in the block
+    const int npan = max(0, min(KT, RT - c0));  // pivot panels in the block
+    const int nprev = min(c0, RT);              // earlier pivot panels
+
+    // the block column from the operator, rows in position order: one
+    // column tile at a time through LDS (a rolled loop, not KT x RTW x 4
+    // inlined operator evaluations), then into the registers
+#pragma unroll
+    for (int c = 0; c < KT; ++c) {
+      if (c < ncol) {
+        for (int e = tid; e < R * 16; e += NT) {
+          const int pos = e >> 4, cc = e & 15;
+          P[pos * kPST + cc] = (T)build_elem(g, sc, leaf, bs, ord[pos], 16 * (c0 + c) + cc);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < RTW; ++i) {
+        const int t = wv + NW * i;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          acc[i][c][q] = (t < RT && c < ncol) ? (double)P[(16 * t + Tile<T>::crow(q, lane)) * kPST + lc]
+                                              : 0.0;
+      }
+      __syncthreads();
+    }
+
+    // U rows of tile j (the pivots of panel j, in pivot order) from its
+    // current values, by the wavefront that owns the tile: through the LDS
+    // buffer `buf` (raw rows in, U rows out, where the others read them)
+    auto make_u = [&](int j, T *buf, const T (&a)[4]) {
+#pragma unroll
+      for (int i = 0; i < RTW; ++i) {
+        if (wv + NW * i != j) continue;
+#pragma unroll
+        for (int c = 0; c < KT; ++c) {
+          if (c < ncol) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) buf[Tile<T>::crow(q, lane) * KW + 16 * c + lc] = (T)acc[i][c][q];
+          }
+        }
+        wave_lds_fence<T>();
+        Acc u[KT];
+#pragma unroll
+        for (int c = 0; c < KT; ++c) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) u[c][q] = 0.0;
+          if (c < ncol) {
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc)
+              u[c] = Mfma<T>::op(a[kc], buf[(4 * kc + lr) * KW + 16 * c + lc], u[c]);
+          }
+        }
+        wave_lds_fence<T>();
+#pragma unroll
+        for (int c = 0; c < KT; ++c) {
+          if (c < ncol) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              buf[Tile<T>::crow(q, lane) * KW + 16 * c + lc] = (T)u[c][q];
+              acc[i][c][q] = (double)(T)u[c][q];
+            }
+          }
+        }
+      }
+    };
+    // multipliers of panel j for the rows of tile t = wv + NW i (negated):
+    // the A operand of that tile's update, gathered through the positions.
+    // In MFMA step kc lane group lr contracts over index 4 lr + kc (the
+    // same pairing in A and B), so a lane's four values are contiguous.
+    auto load_a = [&](int i, int j, T (&a)[4]) {
+      const int row = ord[16 * (wv + NW * i) + lc];
+      const T *src = Ml + tix<T>(row, 16 * j + 4 * lr, CT);
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) a[kc] = -src[kc];
+    };
+    auto mma = [&](int i, const T (&a)[4], const T (&b)[KT][4]) {
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+        if (c < ncol) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) acc[i][c] = Mfma<T>::op(a[kc], b[c][kc], acc[i][c]);
+        }
+      }
+    };
+
+    // updates from the earlier panels, in order.  The multipliers of the
+    // next step for a wavefront's first PF tiles (and the L11^{-1} the next
+    // U needs) are loaded a step ahead, and the barrier orders LDS only, so
+    // those loads stay in flight across it; the other tiles' multipliers
+    // are loaded in the step, behind the first tiles' MFMAs.  The owner of
+    // tile j + 1 takes step j there first and forms U_{j+1} before the next
+    // barrier.
+    T apre[PF][4];
+    T lpre[4];
+    if (nprev > 0) {
+#pragma unroll
+      for (int i = 0; i < PF; ++i) {
+        const int t = wv + NW * i;
+        if (t > 0 && t < RT) load_a(i, 0, apre[i]);
+      }
+      if (wv == 0) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) lpre[kc] = Lg[lc * 16 + 4 * kc + lr];
+        make_u(0, Ub, lpre);
+      }
+      if (nprev > 1 && wv == 1 % NW) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) lpre[kc] = Lg[256 + lc * 16 + 4 * kc + lr];
+      }
+    }
+    for (int j = 0; j < nprev; ++j) {
+      lds_barrier();
+      const T *U = Ub + (j & 1) * 16 * KW;
+      T b[KT][4];
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? U[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
+      }
+      const int jn = j + 1;
+      const bool ahead = jn < nprev && wv == jn % NW;
+      if (ahead) {
+#pragma unroll
+        for (int i = 0; i < RTW; ++i) {
+          if (wv + NW * i != jn) continue;
+          if (i < PF) {
+            mma(i, apre[i < PF ? i : 0], b);
+          } else {
+            T a[4];
+            load_a(i, j, a);
+            mma(i, a, b);
+          }
+        }
+        make_u(jn, Ub + (jn & 1) * 16 * KW, lpre);
+      }
+#pragma unroll
+      for (int i = 0; i < RTW; ++i) {
+        const int t = wv + NW * i;
+        if (!(t > j && t < RT && !(ahead && t == jn))) continue;
+        if (i < PF) {
+          mma(i, apre[i < PF ? i : 0], b);
+        } else {
+          T a[4];
+          load_a(i, j, a);
+          mma(i, a, b);
+        }
+      }
+      if (jn < nprev) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) {
+          const int t = wv + NW * i;
+          if (t > jn && t < RT) load_a(i, jn, apre[i]);
+        }
+        if (jn + 1 < nprev && wv == (jn + 1) % NW) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) lpre[kc] = Lg[(jn + 1) * 256 + lc * 16 + 4 * kc + lr];
+        }
+      }
+    }
+    __syncthreads();
+
+    // this block column's own panels, in turn.  The panel being factored is
+    // always register tile 0: after each panel the block column's tiles
+    // rotate by one, KT times in all, so that every register index stays a
+    // compile-time constant and the tiles end in their order again.
+    if (npan > 0) {
+      const int Rr = R - 16 * c0;
+      for (int r = tid; r < Rr; r += NT) pst[r] = kInfoActive;
+      __syncthreads();
+#pragma unroll 1
+      for (int s = 0; s < KT; ++s) {
+        if (s < npan) {
+          const int k = c0 + s;
+          int *pv = pvs + 16 * s;
+#pragma unroll
+          for (int i = 0; i < RTW; ++i) {
+            const int t = wv + NW * i;
+            if (t >= c0 && t < RT) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                P[(16 * (t - c0) + Tile<T>::crow(q, lane)) * kPST + lc] = (T)acc[i][0][q];
+            }
+          }
+          __syncthreads();
+          if constexpr (NW == 4) {
+            if (wv == 0) {
+              panel_one_wave<T>(P, Rr, k, lane, pv, pst, zeroPiv);
+              wave_lds_fence<T>();
+            }
+          } else {
+            panel_wg<T, NT>(P, Rr, k, pv, pst, zeroPiv, redv, redi);
+          }
+          if (wv == 0) {
+            linv16<T>(P, pv, Lk, lane);
+            if (lane < 16) prow[pv[lane]] = lane;
+            wave_lds_fence<T>();
+            if (lane < 16) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) Lg[k * 256 + r * 16 + lane] = Lk[r * kPST + lane];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int i = 0; i < RTW; ++i) {
+            const int t = wv + NW * i;
+            if (t >= c0 && t < RT) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                acc[i][0][q] = (double)P[(16 * (t - c0) + Tile<T>::crow(q, lane)) * kPST + lc];
+            }
+          }
+          if (s + 1 < ncol) {
+            // raw pivot rows of the block's later column tiles (register
+            // tiles 1, 2, ...) into Ub, U = L11^{-1} of them in place, then
+            // pivot rows take U and the rows still active take -L21 U (L21
+            // from the panel in LDS)
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+              const int t = wv + NW * i;
+              if (t >= c0 && t < RT) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int rp = 16 * (t - c0) + Tile<T>::crow(q, lane);
+                  if (pst[rp] == k) {
+                    const int c = prow[rp];
+#pragma unroll
+                    for (int sp = 1; sp < KT; ++sp)
+                      if (s + sp < ncol) Ub[c * KW + 16 * sp + lc] = (T)acc[i][sp][q];
+                  }
+                }
+              }
+            }
+            __syncthreads();
+            for (int sp = 1 + wv; s + sp < ncol; sp += NW) {
+              const Acc u = tri_apply<T>(Lk, Ub, KW, 16 * sp, lane);
+              wave_lds_fence<T>();
+#pragma unroll
+              for (int q = 0; q < 4; ++q) Ub[Tile<T>::crow(q, lane) * KW + 16 * sp + lc] = (T)u[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+              const int t = wv + NW * i;
+              if (t < c0 || t >= RT) continue;
+              const int ra = 16 * (t - c0) + lc;
+              const bool act = pst[ra] == kInfoActive;
+              T a[4];
+#pragma unroll
+              for (int kc = 0; kc < 4; ++kc) a[kc] = act ? -P[ra * kPST + 4 * kc + lr] : T(0);
+#pragma unroll
+              for (int sp = 1; sp < KT; ++sp) {
+                if (s + sp >= ncol) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int rp = 16 * (t - c0) + Tile<T>::crow(q, lane);
+                  if (pst[rp] == k) acc[i][sp][q] = (double)Ub[prow[rp] * KW + 16 * sp + lc];
+                }
+#pragma unroll
+                for (int kc = 0; kc < 4; ++kc)
+                  acc[i][sp] = Mfma<T>::op(a[kc], Ub[(4 * kc + lr) * KW + 16 * sp + lc], acc[i][sp]);
+              }
+            }
+          }
+          __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < RTW; ++i) {
+          const Acc first = acc[i][0];
+#pragma unroll
+          for (int c = 0; c + 1 < KT; ++c) acc[i][c] = acc[i][c + 1];
+          acc[i][KT - 1] = first;
+        }
+      }
+    }
+
+    // the block column, once, at the rows' places in the work matrix
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      const int t = wv + NW * i;
+      if (t >= RT) continue;
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+        if (c >= ncol) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = ord[16 * t + Tile<T>::crow(q, lane)];
+          Ml[tix<T>(row, 16 * (c0 + c) + lc, CT)] = (T)acc[i][c][q];
+        }
+      }
+    }
+
+    // the pivots of this block column take the positions 16 k + c
+    if (npan > 0) {
+      if (tid < 16 * npan) pvs[tid] = ord[16 * c0 + pvs[tid]];   // positions -> rows
+      __syncthreads();
+      if (tid == 0) {
+        for (int e = 0; e < 16 * npan; ++e) {
+          const int row = pvs[e], target = 16 * c0 + e, src = where[row];
+          const int other = ord[target];
+          ord[target] = row;
+          where[row] = target;
+          ord[src] = other;
+          where[other] = src;
+        }
+      }
+      if (tid < 16 * npan) {
+        const int k = c0 + tid / 16;
+        piv[(size_t)wi * R + 16 * c0 + tid] = pvs[tid];
+        rstep[(size_t)wi * R + pvs[tid]] = k;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) info[leaf] = *zeroPiv;
 }
 
 // ---------------------------------------------------------------------------
@@ -1732,15 +2136,6 @@ __global__ void __launch_bounds__(NT) k_trisolve(Geom g, T *M, const int *piv, c
 // are indexed statically).
 // ---------------------------------------------------------------------------
 constexpr int kDST = 17;   // LDS row stride of the diagonal blocks
-
-// Workgroup barrier ordering LDS accesses only: global loads still in flight
-// (the next step's prefetched operands) are not waited for, as they would be
-// by __syncthreads().
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -2833,6 +3228,44 @@ hipError_t launch_factorP(const Geom &g, int nleaf, T *M, int *piv, int *rstep, 
   return hipGetLastError();
 }
 
+template <typename T>
+size_t factor_ll_lds(const Geom &g, int NW, int KT) {
+  size_t b = sizeof(T) * ((size_t)g.R * kPST + 2 * 16 * 16 * (size_t)KT + 16 * kPST + NW);
+  b += sizeof(int) * (4 * (size_t)g.R + 16 * (size_t)KT + NW + 1);
+  return b;
+}
+
+template <typename T, int NW, int RTW, int PF, int MINB>
+hipError_t launch_ll_t(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
+                       const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  const size_t lds = factor_ll_lds<T>(g, NW, 2);
+  if (lds > kLdsLimit || g.RT > NW * RTW) return hipErrorInvalidValue;
+  hipError_t e = set_lds(k_factor_ll<T, NW, RTW, 2, PF, MINB>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_factor_ll<T, NW, RTW, 2, PF, MINB>), dim3(nleaf), dim3(64 * NW), lds, s,
+                     g, M, piv, rstep, info, sel, bs);
+  return hipGetLastError();
+}
+
+// Left-looking factorisation, 32-column block columns: up to 16 row tiles
+// (R <= 256) with four wavefronts (one of them factors each panel in its
+// registers) and two workgroups per CU; up to 64 row tiles with eight
+// wavefronts.  The tuning chunk selects how many row tiles per wavefront
+// have their multipliers loaded a step ahead: 64 -> 4, 128 -> 8, else 2
+// (measured fastest at p = 16 and p = 32: deeper prefetch spills).
+template <typename T>
+hipError_t launch_factor_ll(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
+                            const BuildSrc &bs, hipStream_t s, const Sel &sel) {
+  const int pf = g.tune_ch == 64 ? 4 : g.tune_ch == 128 ? 8 : 2;
+  if (g.RT <= 16) {
+    if (pf == 2) return launch_ll_t<T, 4, 4, 2, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+    return launch_ll_t<T, 4, 4, 4, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+  }
+  if (pf == 2) return launch_ll_t<T, 8, 8, 2, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+  if (pf == 8) return launch_ll_t<T, 8, 8, 8, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+  return launch_ll_t<T, 8, 8, 4, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+}
+
 template <int RT, int NW, int NS>
 hipError_t launch_rr(const Geom &g, int nleaf, float *M, int *piv, int *rstep, int *info,
                      const BuildSrc &bs, hipStream_t s, const Sel &sel) {
@@ -2876,6 +3309,14 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
                          int *info, int mode, const double *f, const double *ub, hipStream_t s,
                          const Sel &sel) {
   const BuildSrc bs{mode, f, ub};
+  // The left-looking factorisation is the FP64 default above 400 rows
+  // (p >= 23): measured 1.3x (p = 24) to 1.5x (p = 32) faster than panel
+  // pairs there for the whole condensation, slower at p <= 20, and slower in
+  // FP32 at every order (whose work matrices stream half the bytes).
+  if (g.tune_variant == 4 || (g.tune_variant == 0 && !fp32 && g.R > 400)) {
+    if (fp32) return launch_factor_ll<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
+    return launch_factor_ll<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
+  }
   if (fp32 && g.tune_variant == 3 && factor_rr_enabled()) {
     const hipError_t e = launch_factor_rr(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     if (e != hipErrorNotSupported) return e;

@@ -562,3 +562,56 @@ def test_leaf_near_a_dirichlet_resonance(torch):
             assert eS <= bar and eX <= bar and eu <= bar, t
             assert be <= p7_bar(ni), t
     B.close()
+
+
+# --------------------------------------------------------------------------
+# left-looking factorisation (tuning variant 4)
+# --------------------------------------------------------------------------
+LL_ORDERS = [4, 5, 8, 12, 13, 16, 18, 19, 20, 23, 24, 30, 32]
+
+
+@pytest.mark.parametrize("prec", [hps.HPS_FP64, hps.HPS_FP32_REFINE])
+@pytest.mark.parametrize("p", LL_ORDERS)
+def test_condense_left_looking(torch, p, prec):
+    """Variant 4 at every block-column shape: one or two row-tile groups per
+    wavefront, block columns straddling the pivot panels and the right-hand
+    sides, odd and even tile counts; with the body-load column too."""
+    _say(f"left-looking p={p} prec={prec}")
+    prob = _small(p, 2)
+    B = _batch([prob])
+    hps.hps_batch_set_tuning(B.batch, 0, 4, 0)
+    S, w, info, st = B.condense(prec=prec, max_refine=3, sync=True)
+    assert st == hps.HPS_OK and bool((info == 0).all())
+    Xt, _ = B.export()
+    nb, ni = 4 * (p - 2), (p - 2) ** 2
+    Sg, Xg = S.view(-1, nb, nb).cpu().numpy(), Xt.view(-1, nb, ni).cpu().numpy()
+    tol = TOL64 if prec == hps.HPS_FP64 else TOL_MIXED
+    for t in range(prob.nleaf):
+        bl, c = oracle_leaf(prob, t)
+        bar = leaf_bar(bl.Aii, tol)
+        assert relerr(Sg[t], c.S) <= bar, t
+        assert relerr(Xg[t].T, c.X) <= (bar if prec == hps.HPS_FP64 else max(bar, 1e-8)), t
+    B.close()
+    if p < 6:
+        return
+    fp = _forced_problem(p)
+    B = _batch([fp])
+    hps.hps_batch_set_tuning(B.batch, 0, 4, 0)
+    f = B.interior_f()
+    S, w, info, st = B.condense(prec=prec, f=f, max_refine=3, sync=True)
+    assert st == hps.HPS_OK
+    _, h = B.export()
+    Sg, wg, hg = (S.view(-1, nb, nb).cpu().numpy(), w.view(-1, nb).cpu().numpy(),
+                  h.view(-1, ni).cpu().numpy())
+    for t in range(fp.nleaf):
+        bl, c = oracle_leaf(fp, t, oracle_interior_f(fp, t))
+        bar = leaf_bar(bl.Aii, tol)
+        assert relerr(Sg[t], c.S) <= bar and relerr(wg[t], c.w) <= bar and relerr(hg[t], c.h) <= bar
+    # the paper's re-factor recovery on the same variant
+    ub = torch.randn(B.nb_total, dtype=torch.float64, device="cuda")
+    u_rf = B.recover(ub, f=f, refactor=True, sync=True).view(-1, ni).cpu().numpy()
+    ubh = ub.view(-1, nb).cpu().numpy()
+    for t in range(fp.nleaf):
+        bl, c = oracle_leaf(fp, t, oracle_interior_f(fp, t))
+        assert relerr(u_rf[t], lf.recover(c, ubh[t])) <= leaf_bar(bl.Aii, TOL64)
+    B.close()

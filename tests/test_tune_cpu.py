@@ -17,7 +17,7 @@ def test_candidates_respect_kernel_limits():
         assert cands and len(set(cands)) == len(cands)
         ni = (p - 2) ** 2
         for v, c in cands:
-            assert v in (1, 2) and c % 16 == 0 and 0 <= c <= 1024
+            assert v in (1, 2, 4) and c % 16 == 0 and 0 <= c <= 1024
             if v == 2 and ni > 256:
                 assert c in (0, 64, 128)
         assert any(v == 1 for v, _ in cands) and any(v == 2 for v, _ in cands)
