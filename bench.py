@@ -41,7 +41,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # 1.0 against a 1 GiB device copy), keyed by the sha256 prefix of the kernel
 # source it was measured on, the workload and the precision.
 MEASURED_TRAFFIC = {
-    ("41d1c930185dd331", "bumps_32x32_p32", "fp64"): {
+    ("4863889878f58105", "bumps_32x32_p32", "fp64"): {
         "kernel": "k_factor_ll<double, 8, 8, 2, 2, 1>",
         "fetch_bytes": 39800223.479 * 2.0 * 1024, "write_bytes": 8330976.349 * 1.0 * 1024},
 }
@@ -56,11 +56,19 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
+    """sha256 prefix of the kernel source with comments and whitespace
+    removed: edits of comments keep a traffic measurement valid, any change
+    of code invalidates it."""
     import hashlib
+    import re
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "paper_2211_14969_amd", "csrc", "hps_kernels.hip")
-    with open(path, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(path) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = re.sub(r"\s+", " ", src).strip()
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def algorithmic_flops(p: int):

@@ -60,8 +60,10 @@ typedef enum {
 
 typedef enum {
   HPS_FP64 = 0,        /* LU, triangular solves and Schur complement in FP64   */
-  HPS_FP32_REFINE = 1  /* FP32 LU and solves (MFMA), FP64 iterative refinement
-                          of X with an FP64 residual A_ib - A_ii X; S in FP64 */
+  HPS_FP32_REFINE = 1  /* LU and solves on FP32-stored work matrices (tile
+                          products on the FP64 MFMA from FP32 operands), FP64
+                          iterative refinement of X with an FP64 residual
+                          A_ib - A_ii X; S in FP64 */
 } hps_precision;
 
 /* flags */

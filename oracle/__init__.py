@@ -12,16 +12,15 @@ What it computes, and where in the paper (arxiv 2211.14969) each step comes
 from:
 
 * ``cheb``      - the p x p tensor grid of Chebyshev points on a leaf and the
-                  spectral differentiation matrix (Sec. 2, description of the
-                  HPS discretisation: "p x p tensor product mesh of Chebyshev
-                  points", "spectral differentiation").
+                  spectral differentiation matrix (Sec. 2, the description of
+                  the HPS discretisation).
 * ``leaf``      - the dense p^2 x p^2 leaf interaction matrix: the PDE
                   (eqs. (bvp), (var_helm)) collocated at interior nodes and
                   the outward normal derivative (flux) on the leaf edges;
                   static condensation of the interior nodes (Sec. 2, the
                   paragraph before eq. (hps_reduced)), done with a plain
-                  LAPACK LU with partial pivoting (Sec. 2, cost paragraph:
-                  "LU factorization, matrix-matrix multiply"); and the
+                  LAPACK LU with partial pivoting and matrix products (the
+                  leaf operations of Sec. 2, cost paragraph); and the
                   per-leaf recovery of interior values (Sec. 3, after
                   eq. (constant_coeff_helm)).
 * ``interface`` - the reduced system on the leaf edges (eq. (hps_reduced)),

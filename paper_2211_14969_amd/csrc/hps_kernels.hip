@@ -9,8 +9,8 @@
 // precision, so a wavefront loads or stores a whole tile with four fully
 // coalesced 512-byte accesses.
 //
-// Elimination (Sec. 2: "LU factorization, matrix-matrix multiply" on every
-// leaf) is a right-looking blocked LU with partial pivoting over panels of
+// Elimination (the leaf operations of Sec. 2: an LU factorisation and matrix
+// products on every leaf) is a blocked LU with partial pivoting over panels of
 // 16 columns.  Rows are never swapped: a pivot row is retired in place and
 // its step recorded (rstep), so the row permutation is implicit.  The panel
 // is factored in LDS (wavefront + workgroup argmax), the pivot rows of the
@@ -46,20 +46,12 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
-#ifdef HPS_F32_NATIVE_MFMA
-template <>
-struct Mfma<float> {
-  using acc = f4;
-  __device__ static __forceinline__ acc op(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-#else
 // FP32 work matrices take their tile products on the FP64 MFMA: the FP32
 // operands are exact in FP64, so every product is exact and accumulation is
 // FP64 before rounding back to FP32 storage.  (The FP32 16x16x4 instruction
-// rounds its operands more coarsely, which leaves the factorisation too
-// inexact for FP64 refinement to converge on the higher orders.)
+// is true FP32 arithmetic, but its FP32 accumulation over the long inner
+// dimensions of the larger orders left leaves that FP64 refinement could
+// not serve.)
 template <>
 struct Mfma<float> {
   using acc = d4;
@@ -67,16 +59,14 @@ struct Mfma<float> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64((double)a, (double)b, c, 0, 0, 0);
   }
 };
-#endif
 
 // Element (r, c) of a tile-major work matrix with CT column tiles.  Inside a
 // 16 x 16 tile the 256 elements are ordered as the accumulator registers of
-// the 16x16x4 MFMA instruction of that precision: element q*64 + lane holds
-// accumulator register q of that lane.  The two precisions differ (checked
-// on gfx950 with a one-hot probe of the builtins):
-//   f32: row r in register r%4 of lanes 16*(r/4) .. +15, column = lane%16;
-//   f64: row r in register r/4 of lanes 16*(r%4) .. +15, column = lane%16,
-//        which is plain row-major order within the tile.
+// the FP64 16x16x4 MFMA instruction, which both precisions use: element
+// q*64 + lane holds accumulator register q of that lane, i.e. row r in
+// register r/4 of lanes 16*(r%4) .. +15, column = lane%16 -- plain
+// row-major order within the tile.  (The FP32 instruction's accumulators are
+// ordered differently: row r in register r%4 of lanes 16*(r/4) .. +15.)
 // The A (16x4) and B (4x16) operand layouts agree: A[i][k] and B[k][j] sit in
 // lane i + 16k and lane j + 16k.
 template <typename T>
@@ -90,23 +80,8 @@ struct Tile<double> {
     c = w & 15;
   }
 };
-#ifdef HPS_F32_NATIVE_MFMA
-template <>
-struct Tile<float> {
-  __device__ static __forceinline__ int inner(int r, int c) {
-    return ((r & 3) << 6) + (((r >> 2) & 3) << 4) + (c & 15);
-  }
-  __device__ static __forceinline__ int crow(int q, int lane) { return 4 * (lane >> 4) + q; }
-  __device__ static __forceinline__ void rc(int w, int &r, int &c) {
-    const int q = w >> 6, ln = w & 63;
-    r = 4 * (ln >> 4) + q;
-    c = ln & 15;
-  }
-};
-#else
 template <>
 struct Tile<float> : Tile<double> {};   // FP64 MFMA accumulator order
-#endif
 
 template <typename T>
 __device__ __forceinline__ size_t tix(int r, int c, int CT) {
