@@ -110,12 +110,14 @@ hps_status hps_ctx_destroy(hps_ctx *ctx);
  * FP64 X and h kept for recovery, per-leaf flags, and the pass scratch (LU
  * work matrices, pivots, refinement bookkeeping) of the leaves in flight,
  * sized once for the largest mode (FP64 with a body-load column) within the
- * workspace cap (environment HPS_WORKSPACE_MB, default 16 GiB; larger groups
- * are condensed in several passes).  After this call no entry point of the
+ * workspace cap (environment HPS_WORKSPACE_MB, default 32 GiB, shared between
+ * the lanes in proportion to their work; larger groups are condensed in
+ * several passes).  After this call no entry point of the
  * batch allocates or frees device memory, so condense and recover calls may
  * be captured in a HIP graph.  Groups are dealt to up to four lanes (largest
- * work first), each with its own stream and scratch, so that groups of
- * different orders run concurrently.  The descriptor arrays are only read
+ * work first; environment HPS_LANES lowers the cap, 1 = a single stream),
+ * each with its own stream and scratch, so that groups of different orders
+ * run concurrently.  The descriptor arrays are only read
  * when the batch is used, so they must stay valid for the batch's lifetime.
  * Synchronous. */
 hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups,

@@ -127,7 +127,7 @@ size_t env_workspace_bytes() {
     const long long mb = std::atoll(s);
     if (mb > 0) return (size_t)mb << 20;
   }
-  return (size_t)16 << 30;  // 16 GiB of in-flight LU work matrices in total
+  return (size_t)32 << 30;  // 32 GiB of in-flight LU work matrices in total
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -241,6 +241,7 @@ int pass_leaves(const Scratch &s, const hps::Geom &g, size_t per, int nleaf) {
   n = std::min(n, s.max_leaves);
   n = std::min(n, s.pr_elems / (size_t)g.R);
   n = std::min(n, (size_t)nleaf);
+  if (n < (size_t)nleaf && n > 256) n -= n % 256;   // whole rounds over the CUs
   return (int)n;
 }
 
@@ -651,7 +652,13 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
   }
   if (st == HPS_OK) {
     // deal the groups to lanes: largest work first, to the least loaded lane
-    const int nl = std::min<int>(kMaxLanes, (int)b->groups.size());
+    // (HPS_LANES caps the lane count, 1 = one stream)
+    int cap = kMaxLanes;
+    if (const char *v = std::getenv("HPS_LANES")) {
+      const int n = std::atoi(v);
+      if (n >= 1 && n < cap) cap = n;
+    }
+    const int nl = std::min<int>(cap, (int)b->groups.size());
     b->lanes.resize(nl);
     std::vector<int> order(b->groups.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -665,15 +672,23 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
     }
     // each lane's pass scratch, sized once for the largest mode: FP64 work
     // matrices with a body-load column (FP32 passes then fit twice the
-    // leaves, whose bookkeeping is sized for that count)
-    const size_t lane_limit = std::max<size_t>(b->ws_limit / nl, 1);
-    for (Lane &L : b->lanes) {
+    // leaves, whose bookkeeping is sized for that count).  The cap is shared
+    // in proportion to the lanes' work, and a group that needs several
+    // passes takes them in multiples of 256 leaves (whole rounds over the
+    // CUs, so no pass ends with a lone partial round)
+    double total_load = 0.0;
+    for (double l : load) total_load += l;
+    for (size_t li = 0; li < b->lanes.size(); ++li) {
+      Lane &L = b->lanes[li];
+      const double share = total_load > 0.0 ? load[li] / total_load : 1.0 / nl;
+      const size_t lane_limit = std::max<size_t>((size_t)(share * (double)b->ws_limit), 1);
       size_t ws = 0, leaves = 0, prl = 0;
       for (int gi : L.groups) {
         const Group &G = b->groups[gi];
         const hps::Geom g = make_geom(G, G.geom.nb + 1);
         const size_t per64 = work_bytes_per_leaf(g, false);
-        const size_t n64 = std::min<size_t>(std::max<size_t>(1, lane_limit / per64), G.d.nleaf);
+        size_t n64 = std::min<size_t>(std::max<size_t>(1, lane_limit / per64), G.d.nleaf);
+        if (n64 < (size_t)G.d.nleaf && n64 > 256) n64 -= n64 % 256;
         const size_t n32 = std::min<size_t>(2 * n64, G.d.nleaf);
         ws = std::max(ws, n64 * per64);
         leaves = std::max(leaves, n32);
