@@ -211,8 +211,7 @@ hps_status hps_leaf_recover(hps_batch *b, const double *ub, const double *f,
  *                    column held in registers, formed from the operator,
  *                    updated by the earlier panels (multipliers read, never
  *                    rewritten) with rows kept in pivot order, then its own
- *                    panels factored (chunk_cols 64 / 128: four / eight row
- *                    tiles per wavefront loaded a step ahead, else two),
+ *                    panels factored (chunk_cols ignored),
  *                    1 one 16-column panel per trailing pass,
  *                    2 panels in pairs (one trailing pass per 32 columns;
  *                    both panels in LDS when (p-2)^2 <= 256 (FP64: < 256),

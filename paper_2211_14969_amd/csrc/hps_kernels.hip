@@ -323,37 +323,48 @@ __device__ __forceinline__ T abs_key(T v) {
   return (a != a) ? T(INFINITY) : a;  // NaN is picked first, then propagates
 }
 
-// Workgroup-wide elimination of one 16-column panel held in LDS (R > 256):
-// per column, every thread scans its rows, a wavefront reduction and an LDS
-// reduction over the wavefronts find the pivot (largest magnitude among the
-// active rows, ties to the lowest row), and every thread updates its rows.
+// Workgroup-wide elimination of one 16-column panel held in LDS (R > 256),
+// one barrier per column: after the barrier that publishes the wavefronts'
+// candidates for column c, every thread picks the pivot (largest magnitude
+// among the active rows, ties to the lowest row), updates its own rows'
+// columns c ... 15, and right away scans its updated column c + 1 for the
+// next pivot candidate; one barrier then publishes both the updated rows
+// and the new candidates (kept in two slots by column parity, so that a
+// slot is not rewritten while it may still be read).  The pivot row is not
+// touched by the update, so every thread may read it while others update.
 template <typename T, int NT>
 __device__ __forceinline__ void panel_wg(T *P, int R, int k, int *pv, int *rst, int *zeroPiv,
                                          T *redv, int *redi) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int c = 0; c < 16; ++c) {
-    T best = T(-1);
-    int bi = INT_MAX;
-    for (int r = tid; r < R; r += NT) {
-      if (rst[r] != kInfoActive) continue;
-      const T v = abs_key(P[r * kPST + c]);
-      if (v > best) { best = v; bi = r; }
-    }
+  auto publish = [&](T best, int bi, int slot) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const T ob = __shfl_xor(best, off);
       const int oi = __shfl_xor(bi, off);
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
-    __syncthreads();
-    best = redv[0];
-    bi = redi[0];
+    if (lane == 0) { redv[slot * NW + wv] = best; redi[slot * NW + wv] = bi; }
+  };
+  {
+    T best = T(-1);
+    int bi = INT_MAX;
+    for (int r = tid; r < R; r += NT) {
+      if (rst[r] != kInfoActive) continue;
+      const T v = abs_key(P[r * kPST]);
+      if (v > best) { best = v; bi = r; }
+    }
+    publish(best, bi, 0);
+  }
+  __syncthreads();
+  for (int c = 0; c < 16; ++c) {
+    const int slot = c & 1;
+    T best = redv[slot * NW];
+    int bi = redi[slot * NW];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const T ob = redv[w];
-      const int oi = redi[w];
+      const T ob = redv[slot * NW + w];
+      const int oi = redi[slot * NW + w];
       if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
     // R - (16k + c) >= 1 rows are active, so bi is a valid row; the clamp
@@ -366,12 +377,19 @@ __device__ __forceinline__ void panel_wg(T *P, int R, int k, int *pv, int *rst, 
       if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + c + 1;
     }
     const T inv = (pval != T(0)) ? T(1) / pval : T(0);
+    T nbest = T(-1);
+    int nbi = INT_MAX;
     for (int r = tid; r < R; r += NT) {
       if (r == pr || rst[r] != kInfoActive) continue;
       const T l = P[r * kPST + c] * inv;
       P[r * kPST + c] = l;
       for (int cc = c + 1; cc < 16; ++cc) P[r * kPST + cc] -= l * P[pr * kPST + cc];
+      if (c + 1 < 16) {
+        const T v = abs_key(P[r * kPST + c + 1]);
+        if (v > nbest) { nbest = v; nbi = r; }
+      }
     }
+    if (c + 1 < 16) publish(nbest, nbi, slot ^ 1);
     __syncthreads();
   }
 }
@@ -389,12 +407,12 @@ __global__ void __launch_bounds__(NT, 512 / NT) k_factor(Geom g, T *M, int *piv,
   T *P = (T *)smem;                       // [R][kPST]   panel
   T *U = P + (size_t)R * kPST;            // [16][UST]   U12 chunk
   T *Linv = U + 16 * UST;                 // [16][kPST]  inverse of L11
-  T *redv = Linv + 16 * kPST;             // [NW]
-  int *rst = (int *)(redv + NW);          // [R]         retire step
+  T *redv = Linv + 16 * kPST;             // [2][NW]
+  int *rst = (int *)(redv + 2 * NW);      // [R]         retire step
   int *tileAct = rst + R;                 // [RT]
   int *pv = tileAct + RT;                 // [16]
-  int *redi = pv + 16;                    // [NW]
-  int *zeroPiv = redi + NW;               // [1]
+  int *redi = pv + 16;                    // [2][NW]
+  int *zeroPiv = redi + 2 * NW;           // [1]
   T *Ml = M + leaf_stride(g) * wi;
   const LeafScale sc = leaf_scale(g, leaf);
 
@@ -872,13 +890,13 @@ __global__ void __launch_bounds__(NT, MINW) k_factorP(Geom g, T *M, int *piv, in
   T *U = P + (size_t)R * kPST;            // [32][UST]   U12 rows of A (0..15), B (16..31)
   T *LA = U + 32 * UST;                   // [16][kPST]  L11_A^{-1}
   T *LB = LA + 16 * kPST;                 // [16][kPST]  L11_B^{-1}
-  T *redv = LB + 16 * kPST;               // [NW]
-  int *rst = (int *)(redv + NW);          // [R]
+  T *redv = LB + 16 * kPST;               // [2][NW]
+  int *rst = (int *)(redv + 2 * NW);      // [R]
   int *tileAct = rst + R;                 // [RT]
   int *pvA = tileAct + RT;                // [16]
   int *pvB = pvA + 16;                    // [16]
-  int *redi = pvB + 16;                   // [NW]
-  int *zeroPiv = redi + NW;               // [1]
+  int *redi = pvB + 16;                   // [2][NW]
+  int *zeroPiv = redi + 2 * NW;           // [1]
   T *Ml = M + leaf_stride(g) * wi;
   const LeafScale sc = leaf_scale(g, leaf);
 
@@ -1207,7 +1225,14 @@ __device__ __forceinline__ void lds_barrier() {
 // it unchanged; the right-hand-side columns are block columns too, so the
 // forward elimination happens on the way.
 // ---------------------------------------------------------------------------
-template <typename T, int NW, int RTW, int KT, int PF, int MINB>
+// Elements of the LDS panel buffer of k_factor_ll: a panel of R rows, or
+// during the updates from earlier panels each wavefront's slots for the
+// coming step's multipliers (RTW 16 x 16 tiles per wavefront).
+__host__ __device__ constexpr size_t ll_panel_elems(int R, int NW, int RTW) {
+  return (size_t)R * kPST > (size_t)NW * RTW * 256 ? (size_t)R * kPST : (size_t)NW * RTW * 256;
+}
+
+template <typename T, int NW, int RTW, int KT, int MINB>
 __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *piv, int *rstep,
                                                             int *info, Sel sel, BuildSrc bs) {
   constexpr int NT = 64 * NW;
@@ -1219,16 +1244,17 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
   if (!resolve_leaf(sel, leaf)) return;
   const int R = g.R, RT = g.RT, CT = g.CT;
   T *P = (T *)smem;                          // [R][kPST]  panel, rows = positions - 16 c0
-  T *Ub = P + (size_t)R * kPST;              // [2][16][KW] U rows
+  T *Abuf = P;                               // [NW][RTW][256] (shares P: updates only)
+  T *Ub = P + ll_panel_elems(R, NW, RTW);    // [2][16][KW] U rows
   T *Lk = Ub + 2 * 16 * KW;                  // [16][kPST] L11^{-1} of the current panel
-  T *redv = Lk + 16 * kPST;                  // [NW]
-  int *ord = (int *)(redv + NW);             // [R] position -> row
+  T *redv = Lk + 16 * kPST;                  // [2][NW]
+  int *ord = (int *)(redv + 2 * NW);         // [R] position -> row
   int *where = ord + R;                      // [R] row -> position
   int *pst = where + R;                      // [R] (position - 16 c0) -> panel that retired it
   int *prow = pst + R;                       // [R] (position - 16 c0) -> index in its panel's pivots
   int *pvs = prow + R;                       // [KT][16] pivots of this block column's panels
-  int *redi = pvs + 16 * KT;                 // [NW]
-  int *zeroPiv = redi + NW;                  // [1]
+  int *redi = pvs + 16 * KT;                 // [2][NW]
+  int *zeroPiv = redi + 2 * NW;              // [1]
   T *Ml = M + leaf_stride(g) * wi;
   T *Lg = Ml + work_elems(g);                // [RT][16][16] L11^{-1} of every panel
   const LeafScale sc = leaf_scale(g, leaf);
@@ -1311,17 +1337,42 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
         }
       }
     };
-    // multipliers of panel j for the rows of tile t = wv + NW i (negated):
-    // the A operand of that tile's update, gathered through the positions.
-    // In MFMA step kc lane group lr contracts over index 4 lr + kc (the
-    // same pairing in A and B), so a lane's four values are contiguous.
-    auto load_a = [&](int i, int j, T (&a)[4]) {
-      const int row = ord[16 * (wv + NW * i) + lc];
-      const T *src = Ml + tix<T>(row, 16 * j + 4 * lr, CT);
+    // multipliers of panel j for the rows of tile t = wv + NW i, gathered
+    // through the positions straight into this wavefront's LDS slot i
+    // (global-to-LDS loads: no registers held while they are in flight; each
+    // lane's 16 bytes land at the slot base + 16 lane, i.e. the tile in
+    // row-major order)
+    auto dma_a = [&](int i, int j) {
+      const int t = wv + NW * i;
+      T *dst = Abuf + (size_t)(wv * RTW + i) * 256;
+      constexpr int per = 1024 / (int)sizeof(T);   // elements per instruction
+#pragma unroll
+      for (int h = 0; h < 256 / per; ++h) {
+        const int e = h * per + lane * (16 / (int)sizeof(T));
+        const T *src = Ml + tix<T>(ord[16 * t + (e >> 4)], 16 * j + (e & 15), CT);
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)(dst + h * per),
+                                         16, 0, 0);
+      }
+    };
+    // the A operand of tile i (negated) from its slot.  In MFMA step kc lane
+    // group lr contracts over index 4 lr + kc (the same pairing in B), so a
+    // lane reads four consecutive values.
+    auto read_a = [&](int i, T (&a)[4]) {
+      const T *src = Abuf + (size_t)(wv * RTW + i) * 256 + lc * 16 + 4 * lr;
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) a[kc] = -src[kc];
     };
-    auto mma = [&](int i, const T (&a)[4], const T (&b)[KT][4]) {
+    // tile i takes step j's update; its slot then refills with panel jn's
+    // multipliers at once (when the tile needs them), so that load is in
+    // flight during the rest of the step
+    auto mma = [&](int i, const T (&b)[KT][4], int jn) {
+      T a[4];
+      read_a(i, a);
+      if (jn >= 0 && wv + NW * i > jn) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the slot has been read
+        dma_a(i, jn);
+      }
 #pragma unroll
       for (int c = 0; c < KT; ++c) {
         if (c < ncol) {
@@ -1331,20 +1382,18 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
       }
     };
 
-    // updates from the earlier panels, in order.  The multipliers of the
-    // next step for a wavefront's first PF tiles (and the L11^{-1} the next
-    // U needs) are loaded a step ahead, and the barrier orders LDS only, so
-    // those loads stay in flight across it; the other tiles' multipliers
-    // are loaded in the step, behind the first tiles' MFMAs.  The owner of
-    // tile j + 1 takes step j there first and forms U_{j+1} before the next
-    // barrier.
-    T apre[PF][4];
+    // updates from the earlier panels, in order.  Each step's multipliers
+    // are loaded into LDS a step ahead (and the L11^{-1} the next U needs
+    // into registers); the barrier orders LDS only, so those loads stay in
+    // flight across it and each wavefront waits only for its own.  The
+    // owner of tile j + 1 takes step j there first and forms U_{j+1} before
+    // the next barrier.
     T lpre[4];
     if (nprev > 0) {
 #pragma unroll
-      for (int i = 0; i < PF; ++i) {
+      for (int i = 0; i < RTW; ++i) {
         const int t = wv + NW * i;
-        if (t > 0 && t < RT) load_a(i, 0, apre[i]);
+        if (t > 0 && t < RT) dma_a(i, 0);
       }
       if (wv == 0) {
 #pragma unroll
@@ -1358,6 +1407,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
     }
     for (int j = 0; j < nprev; ++j) {
       lds_barrier();
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's loads of step j
       const T *U = Ub + (j & 1) * 16 * KW;
       T b[KT][4];
 #pragma unroll
@@ -1366,39 +1416,20 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
         for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? U[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
       }
       const int jn = j + 1;
+      const int jload = jn < nprev ? jn : -1;
       const bool ahead = jn < nprev && wv == jn % NW;
       if (ahead) {
 #pragma unroll
-        for (int i = 0; i < RTW; ++i) {
-          if (wv + NW * i != jn) continue;
-          if (i < PF) {
-            mma(i, apre[i < PF ? i : 0], b);
-          } else {
-            T a[4];
-            load_a(i, j, a);
-            mma(i, a, b);
-          }
-        }
+        for (int i = 0; i < RTW; ++i)
+          if (wv + NW * i == jn) mma(i, b, jload);
         make_u(jn, Ub + (jn & 1) * 16 * KW, lpre);
       }
 #pragma unroll
       for (int i = 0; i < RTW; ++i) {
         const int t = wv + NW * i;
-        if (!(t > j && t < RT && !(ahead && t == jn))) continue;
-        if (i < PF) {
-          mma(i, apre[i < PF ? i : 0], b);
-        } else {
-          T a[4];
-          load_a(i, j, a);
-          mma(i, a, b);
-        }
+        if (t > j && t < RT && !(ahead && t == jn)) mma(i, b, jload);
       }
       if (jn < nprev) {
-#pragma unroll
-        for (int i = 0; i < PF; ++i) {
-          const int t = wv + NW * i;
-          if (t > jn && t < RT) load_a(i, jn, apre[i]);
-        }
         if (jn + 1 < nprev && wv == (jn + 1) % NW) {
 #pragma unroll
           for (int kc = 0; kc < 4; ++kc) lpre[kc] = Lg[(jn + 1) * 256 + lc * 16 + 4 * kc + lr];
@@ -3041,8 +3072,8 @@ inline int factor_nt(const Geom &g) { return g.R <= 256 ? 256 : 512; }
 template <typename T>
 size_t factor_lds(const Geom &g, int CH) {
   const int NW = factor_nt(g) / 64;
-  size_t b = sizeof(T) * ((size_t)g.R * kPST + 16 * (size_t)(CH + 16) + 16 * kPST + NW);
-  b += sizeof(int) * ((size_t)g.R + g.RT + 16 + NW + 1);
+  size_t b = sizeof(T) * ((size_t)g.R * kPST + 16 * (size_t)(CH + 16) + 16 * kPST + 2 * NW);
+  b += sizeof(int) * ((size_t)g.R + g.RT + 16 + 2 * NW + 1);
   return b;
 }
 
@@ -3154,8 +3185,8 @@ hipError_t launch_factor2(const Geom &g, int nleaf, T *M, int *piv, int *rstep, 
 template <typename T>
 size_t factorP_lds(const Geom &g, int CH) {
   constexpr int NW = 512 / 64;
-  size_t b = sizeof(T) * ((size_t)g.R * kPST + 32 * (size_t)(CH + 16) + 32 * kPST + NW);
-  b += sizeof(int) * ((size_t)g.R + g.RT + 32 + NW + 1);
+  size_t b = sizeof(T) * ((size_t)g.R * kPST + 32 * (size_t)(CH + 16) + 32 * kPST + 2 * NW);
+  b += sizeof(int) * ((size_t)g.R + g.RT + 32 + 2 * NW + 1);
   return b;
 }
 
@@ -3204,41 +3235,33 @@ hipError_t launch_factorP(const Geom &g, int nleaf, T *M, int *piv, int *rstep, 
 }
 
 template <typename T>
-size_t factor_ll_lds(const Geom &g, int NW, int KT) {
-  size_t b = sizeof(T) * ((size_t)g.R * kPST + 2 * 16 * 16 * (size_t)KT + 16 * kPST + NW);
-  b += sizeof(int) * (4 * (size_t)g.R + 16 * (size_t)KT + NW + 1);
+size_t factor_ll_lds(const Geom &g, int NW, int RTW, int KT) {
+  size_t b = sizeof(T) * (ll_panel_elems(g.R, NW, RTW) + 2 * 16 * 16 * (size_t)KT + 16 * kPST + 2 * NW);
+  b += sizeof(int) * (4 * (size_t)g.R + 16 * (size_t)KT + 2 * NW + 1);
   return b;
 }
 
-template <typename T, int NW, int RTW, int PF, int MINB>
+template <typename T, int NW, int RTW, int MINB>
 hipError_t launch_ll_t(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
                        const BuildSrc &bs, hipStream_t s, const Sel &sel) {
-  const size_t lds = factor_ll_lds<T>(g, NW, 2);
+  const size_t lds = factor_ll_lds<T>(g, NW, RTW, 2);
   if (lds > kLdsLimit || g.RT > NW * RTW) return hipErrorInvalidValue;
-  hipError_t e = set_lds(k_factor_ll<T, NW, RTW, 2, PF, MINB>, lds);
+  hipError_t e = set_lds(k_factor_ll<T, NW, RTW, 2, MINB>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_factor_ll<T, NW, RTW, 2, PF, MINB>), dim3(nleaf), dim3(64 * NW), lds, s,
-                     g, M, piv, rstep, info, sel, bs);
+  hipLaunchKernelGGL((k_factor_ll<T, NW, RTW, 2, MINB>), dim3(nleaf), dim3(64 * NW), lds, s, g,
+                     M, piv, rstep, info, sel, bs);
   return hipGetLastError();
 }
 
 // Left-looking factorisation, 32-column block columns: up to 16 row tiles
 // (R <= 256) with four wavefronts (one of them factors each panel in its
 // registers) and two workgroups per CU; up to 64 row tiles with eight
-// wavefronts.  The tuning chunk selects how many row tiles per wavefront
-// have their multipliers loaded a step ahead: 64 -> 4, 128 -> 8, else 2
-// (measured fastest at p = 16 and p = 32: deeper prefetch spills).
+// wavefronts.
 template <typename T>
 hipError_t launch_factor_ll(const Geom &g, int nleaf, T *M, int *piv, int *rstep, int *info,
                             const BuildSrc &bs, hipStream_t s, const Sel &sel) {
-  const int pf = g.tune_ch == 64 ? 4 : g.tune_ch == 128 ? 8 : 2;
-  if (g.RT <= 16) {
-    if (pf == 2) return launch_ll_t<T, 4, 4, 2, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
-    return launch_ll_t<T, 4, 4, 4, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
-  }
-  if (pf == 2) return launch_ll_t<T, 8, 8, 2, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
-  if (pf == 8) return launch_ll_t<T, 8, 8, 8, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
-  return launch_ll_t<T, 8, 8, 4, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+  if (g.RT <= 16) return launch_ll_t<T, 4, 4, 2>(g, nleaf, M, piv, rstep, info, bs, s, sel);
+  return launch_ll_t<T, 8, 8, 1>(g, nleaf, M, piv, rstep, info, bs, s, sel);
 }
 
 template <int RT, int NW, int NS>

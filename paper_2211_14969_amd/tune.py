@@ -37,7 +37,7 @@ def candidates(p: int, prec: int = hps.HPS_FP64) -> List[Tuple[int, int]]:
     variants over their column chunks (the paired one of large work matrices
     only at 64 and 128 columns), for FP32 work matrices of at most 208 rows
     the register-resident variant (which has no chunk), and the left-looking
-    variant with two or four row tiles' multipliers loaded a step ahead."""
+    variant."""
     ni, nb = (p - 2) ** 2, 4 * (p - 2)
     cols = ((ni + 15) // 16) * 16 + ((nb + 1 + 15) // 16) * 16
     chunks = [c for c in (32, 64, 128, 256, 512) if c < cols] + [0]
@@ -49,8 +49,8 @@ def candidates(p: int, prec: int = hps.HPS_FP64) -> List[Tuple[int, int]]:
         out = [(1, c) for c in chunks] + [(2, c) for c in (64, 128) if c < cols] + [(2, 0)]
     if prec == hps.HPS_FP32_REFINE and ((ni + 15) // 16) * 16 <= 208:
         out.append((3, 0))
-    # left-looking, block column in registers (two or four tiles loaded ahead)
-    out += [(4, 0), (4, 64)]
+    # left-looking, block column in registers
+    out.append((4, 0))
     return out
 
 
