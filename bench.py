@@ -312,6 +312,42 @@ def recover_timing(B, steps: int):
                               "precision": "fp64"}}
 
 
+def iface_timing(B, prec, max_refine: int, steps: int):
+    """Time the FP64 interface solve (nested dissection on the device) of a
+    single-problem batch: the factorisation from the leaves' S and one solve
+    for u_b.  Not part of the condensation step."""
+    import torch
+    from paper_2211_14969_amd import hps
+    from paper_2211_14969_amd.harness import InterfaceSolver, dirichlet_data
+    prob = B.groups[0].problem
+    S, w, _, _ = B.condense(prec=prec, max_refine=max_refine, sync=True)
+    g = dirichlet_data(B.groups[0])
+    it = InterfaceSolver(B.ctx, prob)
+    ub = torch.empty_like(w)
+    it.factor(S, sync=True)
+    it.solve(S, w, g, ub, sync=True)
+    out = {}
+    for name, fn in (("factor", lambda: it.factor(S)), ("solve", lambda: it.solve(S, w, g, ub))):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+    plan = it.plan
+    it.close()
+    tf = plan["factor_flop"] / (out["factor"] * 1e-3) / 1e12
+    m = prob.p - 2
+    return {"unknowns": ((prob.nx - 1) * prob.ny + prob.nx * (prob.ny - 1)) * m,
+            "fronts": plan["fronts"], "levels": plan["levels"],
+            "max_separator": plan["max_separator"], "factor_ms": out["factor"],
+            "solve_ms": out["solve"], "factor_flop": plan["factor_flop"],
+            "factor_tflops": tf, "factor_frac_fp64_peak": tf / PEAK_TFLOPS["fp64"],
+            "bytes": plan["bytes"], "precision": "fp64"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +364,8 @@ def main() -> int:
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the accuracy check against the oracle")
     ap.add_argument("--no-recover", action="store_true", help="skip the recovery timing")
+    ap.add_argument("--no-iface", action="store_true",
+                    help="skip the timing of the interface solve")
     ap.add_argument("--workload", default="bumps", choices=tuple(WORKLOADS),
                     help="; ".join(f"{k}: {v[1]}" for k, v in WORKLOADS.items()))
     ap.add_argument("--graph", choices=("auto", "on", "off"), default="auto",
@@ -461,6 +499,10 @@ def main() -> int:
     if not args.no_recover:
         B.condense(prec=prec, max_refine=args.max_refine, sync=True)
         line["recover"] = recover_timing(B, max(3, args.steps // 2))
+
+    if not args.no_iface and len(probs) == 1:
+        line["interface_solve"] = iface_timing(B, prec, args.max_refine, max(3, args.steps // 4))
+        print("# timed the interface solve", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
         print("# timing the CPU oracle", file=sys.stderr, flush=True)

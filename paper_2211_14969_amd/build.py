@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpsleaf.so")
 ARCH = "gfx950"
 
-SOURCES = ["hps_kernels.hip", "hps_abi.hip", "hps_cheb.cpp"]
+SOURCES = ["hps_kernels.hip", "hps_abi.hip", "hps_iface.hip", "hps_cheb.cpp"]
 
 
 def hipcc() -> str:

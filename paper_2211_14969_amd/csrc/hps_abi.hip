@@ -40,6 +40,8 @@ struct hps_ctx {
   std::vector<hipEvent_t> pool;
 };
 
+hipStream_t hps::ctx_stream(const hps_ctx *c) { return c->stream; }
+
 namespace {
 
 constexpr int kMaxLanes = 4;

@@ -4,7 +4,12 @@
 #include <cstddef>
 #include <cstdint>
 
+struct hps_ctx;
+
 namespace hps {
+
+// The stream a context enqueues on (hps_abi.hip).
+hipStream_t ctx_stream(const ::hps_ctx *c);
 
 // One order-p group of leaves as the kernels see it (pointers already offset
 // to the first leaf of the launch).

@@ -3,9 +3,10 @@
 * prepares the device inputs of one or several problems (leaf boxes and the
   coefficient fields sampled at the node coordinates the library reports);
 * calls the library's condense / recover entry points;
-* assembles and solves the reduced interface system on the host (the paper's
-  first solver: SciPy SuperLU with COLAMD, Sec. 3.1) to close the loop for
-  end-to-end checks.  The interface solve is not part of the timed hot path.
+* drives the library's FP64 interface solve (nested dissection on the
+  device) and, for comparison, a host solve of the same reduced system
+  (SciPy SuperLU with COLAMD, Sec. 3.1).  The interface solve is not part of
+  the timed leaf-condensation path.
 """
 from __future__ import annotations
 
@@ -149,6 +150,57 @@ class LeafBatch:
         if getattr(self, "ctx", None):
             hps.hps_ctx_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# interface solve on the device (include/hps_iface.h)
+# ---------------------------------------------------------------------------
+
+def boundary_index(p: int):
+    """Flat grid index (i + p*j) of each boundary slot, in the W, E, S, N order."""
+    r = range(1, p - 1)
+    return ([p * j for j in r] + [p - 1 + p * j for j in r] + [i for i in r]
+            + [i + p * (p - 1) for i in r])
+
+
+def dirichlet_data(G: GroupView):
+    """g at every boundary slot of every leaf of the group, [nleaf, nb] on the
+    device (the interface solve reads only the slots on the outer boundary)."""
+    torch = _torch()
+    idx = torch.tensor(boundary_index(G.p), device=G.xy.device)
+    xy = G.xy[:, idx, :]
+    return G.problem.g(xy[..., 0], xy[..., 1], torch).contiguous()
+
+
+class InterfaceSolver:
+    """The library's nested-dissection solve of the reduced system for one
+    problem (a rectangle of nx x ny leaves of one order)."""
+
+    def __init__(self, ctx: int, problem: Problem):
+        self.problem = problem
+        self.plan = hps.hps_iface_plan(problem.p, problem.nx, problem.ny)
+        self.it = hps.hps_iface_create(ctx, problem.p, problem.nx, problem.ny)
+
+    def factor(self, S, info=None, sync: bool = False, allow=(hps.HPS_OK,)):
+        return hps.hps_iface_factor(self.it, S, info, hps.HPS_SYNC if sync else 0, allow=allow)
+
+    def solve(self, S, w, g, ub=None, sync: bool = False):
+        torch = _torch()
+        if ub is None:
+            ub = torch.empty(g.numel(), dtype=torch.float64, device=g.device)
+        hps.hps_iface_solve(self.it, S, w, g, ub, hps.HPS_SYNC if sync else 0)
+        return ub
+
+    def close(self):
+        if getattr(self, "it", None):
+            hps.hps_iface_destroy(self.it)
+            self.it = None
 
     def __del__(self):
         try:

@@ -37,7 +37,11 @@ EXPORTED = (
     "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
     "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times", "hps_batch_set_tuning",
     "hps_leaf_condense_noalloc", "hps_batch_redo_flags", "hps_batch_lanes",
+    "hps_iface_plan", "hps_iface_plan_fronts", "hps_iface_create", "hps_iface_factor", "hps_iface_solve",
+    "hps_iface_destroy",
 )
+
+HPS_IFACE_MAX_SEPARATOR = 1024
 
 HPS_NOALLOC_SCRATCH_BYTES = 512 << 20
 
@@ -120,6 +124,21 @@ def load(path: str = LIB_PATH):
     L.hps_ctx_set_timing.argtypes = [vp, i]
     L.hps_ctx_phase_times.restype = i
     L.hps_ctx_phase_times.argtypes = [vp, ctypes.POINTER(d), ctypes.POINTER(ip)]
+    L.hps_iface_plan.restype = i
+    L.hps_iface_plan.argtypes = [i, i, i, ctypes.POINTER(ip), ctypes.POINTER(ip),
+                                 ctypes.POINTER(ip), ctypes.POINTER(d),
+                                 ctypes.POINTER(ctypes.c_size_t)]
+    L.hps_iface_plan_fronts.restype = i
+    L.hps_iface_plan_fronts.argtypes = [i, i, i, ctypes.POINTER(ip), ctypes.POINTER(ip),
+                                        ctypes.POINTER(ip)]
+    L.hps_iface_create.restype = i
+    L.hps_iface_create.argtypes = [vp, i, i, i, ctypes.POINTER(vp)]
+    L.hps_iface_factor.restype = i
+    L.hps_iface_factor.argtypes = [vp, vp, vp, i]
+    L.hps_iface_solve.restype = i
+    L.hps_iface_solve.argtypes = [vp, vp, vp, vp, vp, i]
+    L.hps_iface_destroy.restype = i
+    L.hps_iface_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -274,3 +293,46 @@ def hps_ctx_phase_times(ctx: int):
 def hps_batch_set_tuning(batch: int, g: int, factor_variant: int = 0, chunk_cols: int = 0) -> None:
     _check(load().hps_batch_set_tuning(ctypes.c_void_p(batch), int(g), int(factor_variant),
                                        int(chunk_cols)), "hps_batch_set_tuning")
+
+
+# -- interface solve (include/hps_iface.h) ----------------------------------
+
+def hps_iface_plan(p: int, nx: int, ny: int) -> dict:
+    """Host-only plan of the nested-dissection tree (no device call)."""
+    nf, lv, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    fl, by = ctypes.c_double(), ctypes.c_size_t()
+    _check(load().hps_iface_plan(int(p), int(nx), int(ny), ctypes.byref(nf), ctypes.byref(lv),
+                                 ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)),
+           "hps_iface_plan")
+    return {"fronts": nf.value, "levels": lv.value, "max_separator": ms.value,
+            "factor_flop": fl.value, "bytes": by.value}
+
+
+def hps_iface_plan_fronts(p: int, nx: int, ny: int):
+    """Per-front (nS, nE, level) lists of the plan, in factorisation order."""
+    n = hps_iface_plan(p, nx, ny)["fronts"]
+    a, b, c = (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))()
+    _check(load().hps_iface_plan_fronts(int(p), int(nx), int(ny), a, b, c), "hps_iface_plan_fronts")
+    return list(a)[:n], list(b)[:n], list(c)[:n]
+
+
+def hps_iface_create(ctx: int, p: int, nx: int, ny: int) -> int:
+    out = ctypes.c_void_p()
+    _check(load().hps_iface_create(ctypes.c_void_p(ctx), int(p), int(nx), int(ny),
+                                   ctypes.byref(out)), "hps_iface_create")
+    return out.value
+
+
+def hps_iface_factor(it: int, S, info=None, flags: int = 0, allow=(HPS_OK,)) -> int:
+    st = load().hps_iface_factor(ctypes.c_void_p(it), _ptr(_f64(S, "S")), _ptr(info), int(flags))
+    return _check(st, "hps_iface_factor", allow)
+
+
+def hps_iface_solve(it: int, S, w, g, ub, flags: int = 0) -> None:
+    _check(load().hps_iface_solve(ctypes.c_void_p(it), _ptr(_f64(S, "S")), _ptr(_f64(w, "w")),
+                                  _ptr(_f64(g, "g")), _ptr(_f64(ub, "ub")), int(flags)),
+           "hps_iface_solve")
+
+
+def hps_iface_destroy(it: int) -> None:
+    _check(load().hps_iface_destroy(ctypes.c_void_p(it)), "hps_iface_destroy")

@@ -102,3 +102,17 @@ class BarLog:
                 f"leaf {l} {n} {e:.1e}" for (l, n, e, _) in self.raised[:6]) + ")"
         print(msg, file=sys.stderr, flush=True)
         return msg
+
+
+def cond1_estimate(A) -> float:
+    """cond_1 of a sparse matrix: ||A||_1 exactly, ||A^{-1}||_1 by the
+    Hager-Higham block estimator (scipy onenormest) on SuperLU factors.
+    For the FP64 floor of large reduced systems, where a dense cond_2 is out
+    of reach."""
+    import scipy.sparse.linalg as sla
+    lu = sla.splu(A.tocsc(), permc_spec="COLAMD")
+    n = A.shape[0]
+    inv = sla.LinearOperator((n, n), matvec=lu.solve,
+                             rmatvec=lambda x: lu.solve(x, trans="T"), dtype=np.float64)
+    a1 = float(abs(A).sum(axis=0).max())
+    return a1 * float(sla.onenormest(inv))

@@ -2,6 +2,7 @@
 header declares, validates arguments without touching a device, and the
 host-side interface numbering agrees with the oracle's."""
 import ctypes
+import glob
 import os
 import re
 
@@ -13,7 +14,7 @@ from paper_2211_14969_amd import harness
 from oracle import interface as itf
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "hps_leaf.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +26,7 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(hps_[a-z_]+)\s*\(", text)))
 
