@@ -15,8 +15,11 @@ from:
                   spectral differentiation matrix (Sec. 2, the description of
                   the HPS discretisation).
 * ``leaf``      - the dense p^2 x p^2 leaf interaction matrix: the PDE
-                  (eqs. (bvp), (var_helm)) collocated at interior nodes and
-                  the outward normal derivative (flux) on the leaf edges;
+                  (eqs. (bvp), (var_helm), and the general operator with a
+                  mixed term of Sec. 3.2, eq. (chain_rule)) collocated at
+                  interior nodes and the outward normal derivative (flux) on
+                  the leaf edges; with a mixed term the corner values come
+                  from the edges' extrapolants (a reading);
                   static condensation of the interior nodes (Sec. 2, the
                   paragraph before eq. (hps_reduced)), done with a plain
                   LAPACK LU with partial pivoting and matrix products (the

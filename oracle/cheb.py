@@ -12,6 +12,13 @@ c_0 = c_{p-1} = 2 and c_k = 1 otherwise,
 
     D[k, l] = (c_k / c_l) (-1)^(k+l) / (t_k - t_l),     k != l,
     D[k, k] = -sum_{l != k} D[k, l]       (rows of D annihilate constants).
+
+With a mixed derivative in the operator the interior rows reach the four
+leaf corners, which carry no unknown.  Each corner value is then taken from
+its two edges: the degree-(p-3) polynomial through an edge's p-2 nodes
+(endpoints excluded) is evaluated at the corner end (`endpoint_weights`),
+and the two edges' values are averaged (a reading: the paper does not say
+how corners are treated).
 """
 from __future__ import annotations
 
@@ -45,3 +52,23 @@ def diff_matrix(p: int) -> np.ndarray:
     for k in range(p):
         D[k, k] = -sum(D[k, l] for l in range(p) if l != k)
     return D
+
+
+def endpoint_weights(p: int):
+    """Weights (lo, hi), each of length p-2: for values v_1..v_{p-2} at the
+    interior nodes t_1..t_{p-2}, sum_k lo[k] v_k and sum_k hi[k] v_k are the
+    degree-(p-3) interpolant evaluated at t = -1 and t = +1.  Lagrange basis
+    polynomials of the interior nodes: l_k(x) = prod_{m != k} (x - t_m)/(t_k - t_m)."""
+    t = nodes(p)[1:-1]
+    n = t.size
+    lo = np.empty(n)
+    hi = np.empty(n)
+    for k in range(n):
+        a = b = 1.0
+        for m in range(n):
+            if m != k:
+                a *= (-1.0 - t[m]) / (t[k] - t[m])
+                b *= (1.0 - t[m]) / (t[k] - t[m])
+        lo[k] = a
+        hi[k] = b
+    return lo, hi

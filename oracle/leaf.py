@@ -9,11 +9,14 @@ design notes of the repository):
 * interior set I: 1 <= i, j <= p-2, ordered i fastest, so ni = (p-2)^2;
 * boundary set B: the four edges without corners, in the order
   W (i = 0, j up), E (i = p-1, j up), S (j = 0, i up), N (j = p-1, i up),
-  so nb = 4(p-2); corner nodes are not used (with no mixed derivative
-  term no retained row refers to them);
-* interior rows collocate the operator of eq. (var_helm) in reference
-  coordinates,
-      -(a11 u_11 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u = f;
+  so nb = 4(p-2); corner nodes carry no unknown;
+* interior rows collocate the general second-order operator of Sec. 3.2
+  (eq. (chain_rule) is an instance) in reference coordinates,
+      -(a11 u_11 + 2 a12 u_12 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u = f;
+  without the mixed term no interior row refers to a corner; with it, each
+  corner value is replaced by the average of the degree-(p-3) extrapolants
+  along its two edges (cheb.endpoint_weights), which folds the corner
+  columns into A_ib (`fold`);
 * boundary rows are the outward normal derivative (the flux whose
   continuity across leaf edges closes the system, Sec. 2), taken with the
   spectral derivative along the line of nodes normal to the edge:
@@ -34,7 +37,7 @@ import scipy.linalg
 
 from . import cheb
 
-FIELDS = ("a11", "a22", "c1", "c2", "k2b")
+FIELDS = ("a11", "a12", "a22", "c1", "c2", "k2b")
 
 
 def interior_nodes(p: int):
@@ -77,7 +80,8 @@ def sample_coefficients(problem, box, p: int) -> Dict[str, np.ndarray]:
 
 
 def operator(box, p: int, coef: Dict[str, np.ndarray]) -> np.ndarray:
-    """The full p^2 x p^2 leaf matrix L over all nodes (corner rows zero).
+    """The full p^2 x p^2 leaf matrix L over all nodes (corner rows zero;
+    interior rows reach the corner columns only through the mixed term).
 
     `coef[name]` holds the field at every node (flat index i + p*j);
     missing fields take their default (a11 = a22 = 1, others 0)."""
@@ -94,6 +98,7 @@ def operator(box, p: int, coef: Dict[str, np.ndarray]) -> np.ndarray:
         return np.full(p * p, default) if v is None else np.asarray(v, dtype=np.float64)
 
     a11, a22 = field("a11", 1.0), field("a22", 1.0)
+    a12 = field("a12", 0.0)
     c1, c2, k2b = field("c1", 0.0), field("c2", 0.0), field("k2b", 0.0)
 
     L = np.zeros((p * p, p * p))
@@ -104,6 +109,10 @@ def operator(box, p: int, coef: Dict[str, np.ndarray]) -> np.ndarray:
         for l in range(p):           # derivatives along x2: same i
             L[n, i + p * l] -= a22[n] * Dyy[j, l] + c2[n] * Dy[j, l]
         L[n, n] -= k2b[n]
+        if a12[n] != 0.0:            # mixed derivative: every node (k, l)
+            for l in range(p):
+                for k in range(p):
+                    L[n, k + p * l] -= 2.0 * a12[n] * Dx[i, k] * Dy[j, l]
     for j in range(1, p - 1):
         for k in range(p):
             L[0 + p * j, k + p * j] = -Dx[0, k]              # W: -d/dx1
@@ -123,12 +132,47 @@ class Blocks:
     Abb: np.ndarray
 
 
-def blocks(box, p: int, coef: Dict[str, np.ndarray]) -> Blocks:
-    L = operator(box, p, coef)
+def corner_nodes(p: int):
+    """The corners (i, j): SW, SE, NW, NE."""
+    return [(0, 0), (p - 1, 0), (0, p - 1), (p - 1, p - 1)]
+
+
+def corner_map(p: int) -> np.ndarray:
+    """C [4, nb]: corner values (SW, SE, NW, NE) from the boundary slots,
+    each the mean of the extrapolants along its two edges to that end."""
+    m = p - 2
+    lo, hi = cheb.endpoint_weights(p)
+    W, E, S, N = 0, m, 2 * m, 3 * m        # first slot of each edge
+    C = np.zeros((4, 4 * m))
+    # SW: W edge to j = 0, S edge to i = 0
+    C[0, W:W + m] += 0.5 * lo
+    C[0, S:S + m] += 0.5 * lo
+    # SE: E edge to j = 0, S edge to i = p-1
+    C[1, E:E + m] += 0.5 * lo
+    C[1, S:S + m] += 0.5 * hi
+    # NW: W edge to j = p-1, N edge to i = 0
+    C[2, W:W + m] += 0.5 * hi
+    C[2, N:N + m] += 0.5 * lo
+    # NE: E edge to j = p-1, N edge to i = p-1
+    C[3, E:E + m] += 0.5 * hi
+    C[3, N:N + m] += 0.5 * hi
+    return C
+
+
+def fold(L: np.ndarray, p: int) -> Blocks:
+    """The four blocks of a full leaf matrix, with the interior rows' corner
+    columns folded into A_ib through corner_map (the edge rows never refer to
+    a corner: each takes its derivative along an interior grid line)."""
     I = flat(p, interior_nodes(p))
     B = flat(p, boundary_nodes(p))
-    return Blocks(Aii=L[np.ix_(I, I)], Aib=L[np.ix_(I, B)],
+    Cn = flat(p, corner_nodes(p))
+    Aib = L[np.ix_(I, B)] + L[np.ix_(I, Cn)] @ corner_map(p)
+    return Blocks(Aii=L[np.ix_(I, I)], Aib=Aib,
                   Abi=L[np.ix_(B, I)], Abb=L[np.ix_(B, B)])
+
+
+def blocks(box, p: int, coef: Dict[str, np.ndarray]) -> Blocks:
+    return fold(operator(box, p, coef), p)
 
 
 @dataclass

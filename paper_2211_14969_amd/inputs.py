@@ -10,11 +10,11 @@ The problems follow the paper's model problem, the variable-coefficient
 Helmholtz operator  A u = -Lap u - kappa^2 b(x) u  (Sec. 1, eq. (var_helm)),
 written in reference coordinates as
 
-    A u = -(a11 u_11 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u,
+    A u = -(a11 u_11 + 2 a12 u_12 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u,
 
-with a11 = a22 = 1, c1 = c2 = 0 and k2b = kappa^2 b on a plain square.  The
-mixed term a12 u_12 of the general operator (Sec. 3.2, eq. (chain_rule)) is
-not represented: every workload here has an orthogonal map, so a12 == 0.
+with a11 = a22 = 1, a12 = c1 = c2 = 0 and k2b = kappa^2 b on a plain square;
+the quarter annulus and the paper's curved domain come from maps of the unit
+square (the curved one with a mixed term, Sec. 3.2, eq. (chain_rule)).
 
 Every function takes the array namespace ``xp`` (``numpy`` or ``torch``) so
 that the same definition is evaluated on the host or on the device.
@@ -29,7 +29,7 @@ import numpy as np
 
 CoefFn = Callable[..., object]
 
-FIELDS = ("a11", "a22", "c1", "c2", "k2b")
+FIELDS = ("a11", "a12", "a22", "c1", "c2", "k2b")
 
 
 @dataclass
@@ -174,6 +174,38 @@ def annulus(p: int = 20, ntheta: int = 128, nr: int = 16, kappa: float = 150.0) 
         name=f"annulus_{ntheta}x{nr}_p{p}", nx=ntheta, ny=nr, p=p, kappa=kappa,
         coef={"a11": a11, "c2": c2, "k2b": _const(kappa * kappa)},
         g=sol, exact=sol, meta={"map": "theta=(pi/2)x1, r=1+x2"},
+    )
+
+
+def curved(p: int = 16, n: int = 8, kappa: float = 20.0, theta: float = 0.6,
+           data: str = "wave") -> Problem:
+    """The paper's curved domain (Sec. 3.2, eq. (parametrization)): the image
+    of the unit square under (x1, x2) -> (x1, x2 / psi(x1)), psi(z) = 1 -
+    sin(z)/4.  Pulled back to the square, -Lap u - kappa^2 u = 0 becomes
+    eq. (chain_rule):
+        a11 = 1, a12 = psi' x2 / psi, a22 = (psi' x2 / psi)^2 + psi^2,
+        c2 = psi'' x2 / psi, k2b = kappa^2.
+    data="wave": g is the plane wave cos(kappa (y1 cos(theta) + y2 sin(theta)))
+    in the physical coordinates y = (x1, x2 / psi(x1)), an exact solution;
+    data="one": u = 1 on the boundary, the paper's Dirichlet data."""
+    psi = lambda x, xp: 1.0 - 0.25 * xp.sin(x)
+    dpsi = lambda x, xp: -0.25 * xp.cos(x)
+    ddpsi = lambda x, xp: 0.25 * xp.sin(x)
+    a12 = lambda x, y, xp: dpsi(x, xp) * y / psi(x, xp)
+    a22 = lambda x, y, xp: (dpsi(x, xp) * y / psi(x, xp)) ** 2 + psi(x, xp) ** 2
+    c2 = lambda x, y, xp: ddpsi(x, xp) * y / psi(x, xp)
+    ct, st = math.cos(theta), math.sin(theta)
+    wave = lambda x, y, xp: xp.cos(kappa * (x * ct + y / psi(x, xp) * st))
+    if data == "wave":
+        g, exact = wave, wave
+    elif data == "one":
+        g, exact = (lambda x, y, xp: xp.zeros_like(x) + 1.0), None
+    else:
+        raise ValueError(data)
+    return Problem(
+        name=f"curved_{n}x{n}_p{p}", nx=n, ny=n, p=p, kappa=kappa,
+        coef={"a12": a12, "a22": a22, "c2": c2, "k2b": _const(kappa * kappa)},
+        g=g, exact=exact, meta={"map": "(x1, x2/psi(x1)), psi = 1 - sin(x1)/4", "data": data},
     )
 
 

@@ -81,3 +81,37 @@ def test_mutation_wrong_endpoint_weight_is_caught():
                 D[k, l] = (-1.0) ** (k + l) / (t[k] - t[l])
         D[k, k] = -sum(D[k, l] for l in range(p) if l != k)
     assert _poly_exactness_error(D, t, p) > 1e-2
+
+
+# -- corner extrapolation weights (used when the operator has a mixed term) --
+
+@pytest.mark.parametrize("p", [4, 5, 8, 13, 20, 32])
+def test_endpoint_weights_exact_to_degree_p_minus_3(p):
+    lo, hi = cheb.endpoint_weights(p)
+    t = cheb.nodes(p)[1:-1]
+    for d in range(p - 2):                     # degree <= p-3: exact
+        assert abs(lo @ t ** d - (-1.0) ** d) <= 1e-11 * max(1.0, np.abs(lo).sum())
+        assert abs(hi @ t ** d - 1.0) <= 1e-11 * max(1.0, np.abs(hi).sum())
+    # degree p-2 is not reproduced: t^(p-2) minus its interpolant at the p-2
+    # nodes is the node polynomial prod_m (t - t_m), so the extrapolant at
+    # -1 misses (-1)^(p-2) by exactly prod_m (-1 - t_m)
+    d = p - 2
+    miss = np.prod(-1.0 - t)
+    assert abs((-1.0) ** d - lo @ t ** d - miss) <= 1e-11 * max(1.0, abs(miss))
+    assert miss != 0.0
+
+
+@pytest.mark.parametrize("p", [6, 9, 16])
+def test_endpoint_weights_symmetry(p):
+    lo, hi = cheb.endpoint_weights(p)
+    assert np.allclose(hi, lo[::-1], rtol=0, atol=1e-12 * np.abs(lo).max())
+    # the nearest node dominates: extrapolation from Lobatto interior points
+    assert np.argmax(np.abs(lo)) == 0 and np.argmax(np.abs(hi)) == p - 3
+
+
+def test_endpoint_weights_p4_by_hand():
+    # p = 4: interior nodes -1/2, 1/2; the line through them at -1 gives
+    # 3/2 v_1 - 1/2 v_2
+    lo, hi = cheb.endpoint_weights(4)
+    assert np.allclose(lo, [1.5, -0.5], atol=1e-15)
+    assert np.allclose(hi, [-0.5, 1.5], atol=1e-15)

@@ -52,6 +52,9 @@ class Poly:
     def dyy(self, x, y):
         return self._eval(x, y, 0, 2)
 
+    def dxy(self, x, y):
+        return self._eval(x, y, 1, 1)
+
 
 def _coef(X, Y):
     return {
@@ -63,20 +66,27 @@ def _coef(X, Y):
     }
 
 
-def _manufactured(p, box, seed=0, coef_fn=_coef, operator=lf.operator):
+def _coef_mixed(X, Y):
+    c = _coef(X, Y)
+    c["a12"] = 0.35 * np.cos(X - 2 * Y) + 0.1
+    return c
+
+
+def _manufactured(p, box, seed=0, coef_fn=_coef, operator=lf.operator, deg=None, fold=lf.fold):
     rng = np.random.default_rng(seed)
-    deg = p - 1
+    deg = p - 1 if deg is None else deg
     c = rng.standard_normal((deg + 1, deg + 1))
     c /= (1.0 + np.add.outer(np.arange(deg + 1), np.arange(deg + 1))) ** 2
     u = Poly(c, box)
     X, Y = lf.grid(box, p)
     coef = coef_fn(X, Y)
-    f = -(coef["a11"] * u.dxx(X, Y) + coef["a22"] * u.dyy(X, Y)
+    a12 = coef.get("a12", np.zeros_like(X))
+    f = -(coef["a11"] * u.dxx(X, Y) + 2.0 * a12 * u.dxy(X, Y) + coef["a22"] * u.dyy(X, Y)
           + coef["c1"] * u.dx(X, Y) + coef["c2"] * u.dy(X, Y)) - coef["k2b"] * u(X, Y)
     L = operator(box, p, coef)
     I = lf.flat(p, lf.interior_nodes(p))
     B = lf.flat(p, lf.boundary_nodes(p))
-    bl = lf.Blocks(Aii=L[np.ix_(I, I)], Aib=L[np.ix_(I, B)], Abi=L[np.ix_(B, I)], Abb=L[np.ix_(B, B)])
+    bl = fold(L, p)
     cond = lf.condense(bl, f[I])
     ub = u(X[B], Y[B])
     ui = lf.recover(cond, ub)
@@ -188,4 +198,73 @@ def _k2b_sign(box, p, coef):
 @pytest.mark.parametrize("mutant", [_flip_east, _drop_c1, _swap_h, _k2b_sign])
 def test_planted_mistakes_are_caught(mutant):
     err_u, err_flux = _manufactured(8, BOX, operator=mutant)
+    assert max(err_u, err_flux) > 1e-4
+
+
+
+# -- the mixed term and the corners (general operator, Sec. 3.2) ------------
+# With a12 != 0 the interior rows reach the corners, whose values come from
+# the edges' degree-(p-3) extrapolants: exact for polynomials of degree <=
+# p-3 in each variable, so such a manufactured solution is reproduced to
+# rounding.
+
+@pytest.mark.parametrize("p", [5, 6, 8, 10, 12])
+def test_manufactured_polynomial_with_mixed_term(p):
+    err_u, err_flux = _manufactured(p, BOX, coef_fn=_coef_mixed, deg=p - 3)
+    assert err_u < 1e-10, err_u
+    assert err_flux < 1e-9, err_flux
+
+
+def test_mixed_term_needs_the_corners():
+    # degree p-1 is beyond what the corner extrapolation reproduces: the
+    # mixed term then sees the extrapolation error (the a12 == 0 operator
+    # does not, which the pin above relies on)
+    err_u, _ = _manufactured(8, BOX, coef_fn=_coef_mixed, deg=7)
+    assert err_u > 1e-8
+    err_u0, _ = _manufactured(8, BOX, coef_fn=_coef, deg=7)
+    assert err_u0 < 1e-11
+
+
+def _mixed_no_two(box, p, coef):
+    c = dict(coef)
+    c["a12"] = 0.5 * coef["a12"]
+    return lf.operator(box, p, c)
+
+
+def _mixed_xx(box, p, coef):
+    # mixed term with the x1 derivative twice (transposed operand)
+    L = lf.operator(box, p, {k: v for k, v in coef.items() if k != "a12"})
+    x0, x1, y0, y1 = box
+    D = lf.cheb.diff_matrix(p)
+    Dx = (2.0 / (x1 - x0)) * D
+    for (i, j) in lf.interior_nodes(p):
+        n = i + p * j
+        for l in range(p):
+            for k in range(p):
+                L[n, k + p * l] -= 2.0 * coef["a12"][n] * Dx[i, k] * Dx[j, l]
+    return L
+
+
+def _fold_swapped(L, p):
+    bl = lf.fold(L, p)
+    I = lf.flat(p, lf.interior_nodes(p))
+    Cn = lf.flat(p, lf.corner_nodes(p))
+    C = lf.corner_map(p)
+    # corners taken with the weights of the opposite end
+    return lf.Blocks(Aii=bl.Aii, Aib=bl.Aib - L[np.ix_(I, Cn)] @ C + L[np.ix_(I, Cn)] @ C[::-1],
+                     Abi=bl.Abi, Abb=bl.Abb)
+
+
+def _no_fold(L, p):
+    I = lf.flat(p, lf.interior_nodes(p))
+    B = lf.flat(p, lf.boundary_nodes(p))
+    return lf.Blocks(Aii=L[np.ix_(I, I)], Aib=L[np.ix_(I, B)], Abi=L[np.ix_(B, I)],
+                     Abb=L[np.ix_(B, B)])
+
+
+@pytest.mark.parametrize("operator,fold", [(_mixed_no_two, lf.fold), (_mixed_xx, lf.fold),
+                                           (lf.operator, _fold_swapped), (lf.operator, _no_fold)])
+def test_planted_mixed_term_mistakes_are_caught(operator, fold):
+    err_u, err_flux = _manufactured(8, BOX, coef_fn=_coef_mixed, deg=5, operator=operator,
+                                    fold=fold)
     assert max(err_u, err_flux) > 1e-4
