@@ -9,10 +9,15 @@
  * its boundary, with A a second-order elliptic operator.  In the reference
  * coordinates of a leaf box this library collocates
  *
- *     A u = -(a11 u_11 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u
+ *     A u = -(a11 u_11 + 2 a12 u_12 + a22 u_22 + c1 u_1 + c2 u_2) - k2b u
  *
  * (the variable-coefficient Helmholtz operator has a11 = a22 = 1,
- * c1 = c2 = 0, k2b = kappa^2 b).  The mixed term a12 u_12 is not supported.
+ * a12 = c1 = c2 = 0, k2b = kappa^2 b; a mapped domain such as the curved one
+ * of Sec. 3.2, eq. (chain_rule), brings the mixed term).  With a12 the
+ * interior rows reach the leaf corners, which carry no unknown: each corner
+ * value is taken as the mean of the degree-(p-3) polynomials through its two
+ * edges' nodes, evaluated at the corner, which folds the corner columns into
+ * A_ib.  Operators with a12 are condensed in FP64 only.
  *
  * Discretisation (Sec. 2): each leaf carries a p x p tensor grid of Chebyshev
  * extreme points; the PDE is collocated at the (p-2)^2 interior nodes by
@@ -82,10 +87,11 @@ typedef enum {
 /* One group of leaves sharing the order p (a whole problem, or one order
  * class of a multi-problem batch).
  *   box : device [nleaf][4] = x0, x1, y0, y1 of each leaf (reference coords)
- *   a11, a22, c1, c2, k2b : device [nleaf][p*p] samples at every node (flat
- *         index i + p*j), or NULL for the default (a11 = a22 = 1, others 0).
- *         Sample them at the coordinates returned by hps_leaf_nodes.
- *   a12 : must be NULL (the mixed derivative is not supported).          */
+ *   a11, a12, a22, c1, c2, k2b : device [nleaf][p*p] samples at every node
+ *         (flat index i + p*j), or NULL for the default (a11 = a22 = 1,
+ *         others 0).  Sample them at the coordinates returned by
+ *         hps_leaf_nodes.  A group with a12 must be condensed with HPS_FP64
+ *         (HPS_FP32_REFINE returns HPS_ERR_INVALID).                      */
 typedef struct {
   int p;
   int nleaf;

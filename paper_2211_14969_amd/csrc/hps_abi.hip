@@ -177,8 +177,10 @@ hps::Geom make_geom(const hps_leaf_desc &d, const double *dtab, int nrhs) {
   g.c1 = d.c1;
   g.c2 = d.c2;
   g.k2b = d.k2b;
+  g.a12 = d.a12;
   g.D = dtab + d.p;
   g.D2 = dtab + d.p + (size_t)d.p * d.p;
+  g.E = dtab + d.p + 2 * (size_t)d.p * d.p;
   g.tune_variant = 0;
   g.tune_ch = 0;
   return g;
@@ -201,6 +203,7 @@ hps::Geom shift(const hps::Geom &g, int l0) {
   if (g.c1) s.c1 = g.c1 + pp * l0;
   if (g.c2) s.c2 = g.c2 + pp * l0;
   if (g.k2b) s.k2b = g.k2b + pp * l0;
+  if (g.a12) s.a12 = g.a12 + pp * l0;
   return s;
 }
 
@@ -435,8 +438,11 @@ hps_status check_condense_args(hps_batch *b, hps_precision prec, int max_refine,
   if (max_refine < 0 || max_refine > 16) return HPS_ERR_INVALID;
   const bool fp32 = prec == HPS_FP32_REFINE;
   const int extra = f ? 1 : 0;
-  for (const Group &G : b->groups)
+  for (const Group &G : b->groups) {
+    // the FP32 path's structured residual has no mixed term
+    if (fp32 && G.d.a12) return HPS_ERR_INVALID;
     if (hps::factor_lds_bytes(make_geom(G, G.geom.nb + extra), fp32) == 0) return HPS_ERR_INVALID;
+  }
   return HPS_OK;
 }
 
@@ -598,8 +604,7 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
   long long total = 0;
   for (int i = 0; i < ngroups; ++i) {
     const hps_leaf_desc &d = groups[i];
-    if (d.p < HPS_P_MIN || d.p > HPS_P_MAX || d.nleaf <= 0 || !d.box || d.a12)
-      return HPS_ERR_INVALID;
+    if (d.p < HPS_P_MIN || d.p > HPS_P_MAX || d.nleaf <= 0 || !d.box) return HPS_ERR_INVALID;
     total += d.nleaf;
   }
   if (total > (1LL << 30)) return HPS_ERR_INVALID;
@@ -617,8 +622,9 @@ hps_status hps_leaf_build(hps_ctx *ctx, const hps_leaf_desc *groups, int ngroups
     G.tune_variant = 0;
     G.tune_ch = 0;
     const int p = G.d.p;
-    std::vector<double> tab((size_t)p + 2 * (size_t)p * p);
-    hps::cheb_tables(p, tab.data(), tab.data() + p, tab.data() + p + (size_t)p * p);
+    std::vector<double> tab(hps::cheb_table_size(p));
+    hps::cheb_tables(p, tab.data(), tab.data() + p, tab.data() + p + (size_t)p * p,
+                     tab.data() + p + 2 * (size_t)p * p);
     if (hipMalloc(&G.dtab, sizeof(double) * tab.size()) != hipSuccess) {
       st = HPS_ERR_OOM;
       break;

@@ -9,6 +9,11 @@
 // k != l, and each diagonal entry is minus the sum of the rest of its row
 // (so D maps constants to zero).  The second derivative is D*D, formed in
 // extended precision and rounded once.
+//
+// Corner weights (for operators with a mixed term, whose interior rows reach
+// the leaf corners): E[0][q] and E[1][q], q = 0..p-3, evaluate at t = -1 and
+// t = +1 the degree-(p-3) polynomial through the values at the p-2 interior
+// points t_1..t_{p-2} (Lagrange basis of those points).
 #include <cmath>
 #include <vector>
 
@@ -16,7 +21,7 @@
 
 namespace hps {
 
-void cheb_tables(int p, double *t, double *D, double *D2) {
+void cheb_tables(int p, double *t, double *D, double *D2, double *E) {
   const int n = p - 1;
   const long double pi = 3.141592653589793238462643383279502884L;
   // sin form: exactly antisymmetric about the midpoint
@@ -44,6 +49,19 @@ void cheb_tables(int p, double *t, double *D, double *D2) {
       for (int q = 0; q < p; ++q) acc += Dl[(size_t)k * p + q] * Dl[(size_t)q * p + l];
       D2[(size_t)k * p + l] = (double)acc;
     }
+  const int m = p - 2;
+  for (int q = 0; q < m; ++q) {
+    long double lo = 1.0L, hi = 1.0L;
+    const long double tq = (long double)t[q + 1];
+    for (int r = 0; r < m; ++r) {
+      if (r == q) continue;
+      const long double tr = (long double)t[r + 1];
+      lo *= (-1.0L - tr) / (tq - tr);
+      hi *= (1.0L - tr) / (tq - tr);
+    }
+    E[q] = (double)lo;
+    E[m + q] = (double)hi;
+  }
 }
 
 }  // namespace hps

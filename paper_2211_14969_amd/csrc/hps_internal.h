@@ -25,8 +25,10 @@ struct Geom {
   int nrhs;     // right-hand-side columns in use
   const double *box;                        // [nleaf][4]
   const double *a11, *a22, *c1, *c2, *k2b;  // [nleaf][p*p] or nullptr
+  const double *a12;                        // [nleaf][p*p] or nullptr (mixed term)
   const double *D;                          // [p][p]  d/dt on [-1, 1]
   const double *D2;                         // [p][p]  D*D
+  const double *E;                          // [2][p-2] corner extrapolation weights
   int tune_variant;   // factorisation: 0 automatic, 1 one panel per pass, 2 panel pairs,
                       // 3 register-resident (FP32, R <= 208)
   int tune_ch;        // column chunk of the U12 / trailing passes (0 automatic)
@@ -116,6 +118,8 @@ hipError_t launch_copy_info(const int *src, int *dst, int n, hipStream_t s);
 size_t factor_lds_bytes(const Geom &g, bool fp32);
 
 // Host tables (hps_cheb.cpp).
-void cheb_tables(int p, double *t, double *D, double *D2);
+// t [p], D [p*p], D2 [p*p], E [2][p-2]; cheb_table_size(p) doubles in all.
+void cheb_tables(int p, double *t, double *D, double *D2, double *E);
+inline size_t cheb_table_size(int p) { return (size_t)p + 2 * (size_t)p * p + 2 * (size_t)(p - 2); }
 
 }  // namespace hps

@@ -132,7 +132,8 @@ __device__ __forceinline__ LeafScale leaf_scale(const Geom &g, int leaf) {
 // Entry of the collocated operator in the row of interior node (i, j) and
 // the column of node (k, l):
 //   -(a11 d11 + c1 d1) along x1, -(a22 d22 + c2 d2) along x2, -k2b on the
-// diagonal, with d1 = (2/hx) D, d11 = (2/hx)^2 D^2 (likewise in x2).
+// diagonal, with d1 = (2/hx) D, d11 = (2/hx)^2 D^2 (likewise in x2), and
+// with a mixed term -2 a12 d1x[i][k] d1y[j][l] at every node (k, l).
 __device__ __forceinline__ double opval(const Geom &g, const double *sD,
                                         const double *sD2, LeafScale sc,
                                         size_t nbase, int i, int j, int k, int l) {
@@ -150,6 +151,36 @@ __device__ __forceinline__ double opval(const Geom &g, const double *sD,
     v -= a * (sc.sy * sc.sy) * sD2[j * p + l] + c * sc.sy * sD[j * p + l];
   }
   if (k == i && l == j && g.k2b) v -= g.k2b[n];
+  if (g.a12) v -= 2.0 * g.a12[n] * (sc.sx * sD[i * p + k]) * (sc.sy * sD[j * p + l]);
+  return v;
+}
+
+// Entry of A_ib: the row of interior node (i, j), the column of boundary slot
+// b.  With a mixed term the row also reaches the leaf corners, which carry no
+// unknown: each corner value is the mean of the degree-(p-3) extrapolants
+// along its two edges (weights E[0] to an edge's low end, E[1] to its high
+// end), so an edge slot collects half of each of its edge's two corners.
+__device__ __forceinline__ double aib_elem(const Geom &g, const double *sD, const double *sD2,
+                                           LeafScale sc, size_t nbase, int i, int j, int b) {
+  const int p = g.p, m = g.m;
+  int k, l;
+  bnode(b, m, p, k, l);
+  double v = opval(g, sD, sD2, sc, nbase, i, j, k, l);
+  if (g.a12) {
+    const int s = b / m, q = b - s * m;
+    int k0, l0, k1, l1;   // the edge's corners at its low and high ends
+    if (s < 2) {          // W / E: along x2
+      k0 = k1 = (s == 0) ? 0 : p - 1;
+      l0 = 0;
+      l1 = p - 1;
+    } else {              // S / N: along x1
+      l0 = l1 = (s == 2) ? 0 : p - 1;
+      k0 = 0;
+      k1 = p - 1;
+    }
+    v += 0.5 * (opval(g, sD, sD2, sc, nbase, i, j, k0, l0) * g.E[q] +
+                opval(g, sD, sD2, sc, nbase, i, j, k1, l1) * g.E[m + q]);
+  }
   return v;
 }
 
@@ -180,23 +211,23 @@ __device__ __forceinline__ double build_elem(const Geom &g, LeafScale sc, int le
   if (c < ni) {
     const int lc0 = (c * g.mdiv) >> 16;
     const int k = c - lc0 * m + 1, l = lc0 + 1;
-    if (k != i && l != j) return 0.0;            // not on the row's grid lines
+    if (!g.a12 && k != i && l != j) return 0.0;  // not on the row's grid lines
     return opval(g, g.D, g.D2, sc, nbase, i, j, k, l);
   }
   if (c < R) return 0.0;
   const int jr = c - R;
   if (bs.mode == RHS_CONDENSE) {
-    if (jr < nb) {
-      int k, l;
-      bnode(jr, m, p, k, l);
-      return opval(g, g.D, g.D2, sc, nbase, i, j, k, l);
-    }
+    if (jr < nb) return aib_elem(g, g.D, g.D2, sc, nbase, i, j, jr);
     if (jr == nb && bs.f) return bs.f[(size_t)leaf * ni + r];
     return 0.0;
   }
   if (jr != 0) return 0.0;
   const double *u = bs.ub + (size_t)leaf * nb;  // RHS_REFACTOR: f_i - A_ib u_b
   double v = bs.f ? bs.f[(size_t)leaf * ni + r] : 0.0;
+  if (g.a12) {   // the mixed term couples the row to every slot
+    for (int b = 0; b < nb; ++b) v -= aib_elem(g, g.D, g.D2, sc, nbase, i, j, b) * u[b];
+    return v;
+  }
   v -= opval(g, g.D, g.D2, sc, nbase, i, j, 0, j) * u[j - 1];
   v -= opval(g, g.D, g.D2, sc, nbase, i, j, p - 1, j) * u[m + j - 1];
   v -= opval(g, g.D, g.D2, sc, nbase, i, j, i, 0) * u[2 * m + i - 1];
@@ -3006,9 +3037,7 @@ __global__ void __launch_bounds__(256) k_operator(Geom g, double *Aii, double *A
   if (Aib)
     for (int e = threadIdx.x; e < ni * nb; e += blockDim.x) {
       const int r = e / nb, b = e - r * nb;
-      int k, l;
-      bnode(b, m, p, k, l);
-      Aib[(size_t)leaf * ni * nb + e] = opval(g, sD, sD2, sc, nbase, r % m + 1, r / m + 1, k, l);
+      Aib[(size_t)leaf * ni * nb + e] = aib_elem(g, sD, sD2, sc, nbase, r % m + 1, r / m + 1, b);
     }
   // boundary rows: outward normal derivative along the line through the node
   auto brow = [&](int b, int k, int l) -> double {

@@ -418,8 +418,8 @@ def test_invalid_arguments_enqueue_nothing(torch):
     with pytest.raises(hps.HpsError):
         hps.hps_leaf_recover(B.batch, S, None, S)    # recover before any condense
     box = torch.zeros((1, 4), dtype=torch.float64, device="cuda")
-    for bad in ({"p": 3, "box": box}, {"p": 33, "box": box},
-                {"p": 8, "box": box, "a12": torch.zeros((1, 64), dtype=torch.float64, device="cuda")}):
+    empty = torch.zeros((0, 4), dtype=torch.float64, device="cuda")
+    for bad in ({"p": 3, "box": box}, {"p": 33, "box": box}, {"p": 8, "box": empty}):
         with pytest.raises(hps.HpsError):
             hps.hps_leaf_build(B.ctx, [bad])
     B.close()
