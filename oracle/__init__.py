@@ -26,6 +26,10 @@ from:
                   leaf operations of Sec. 2, cost paragraph); and the
                   per-leaf recovery of interior values (Sec. 3, after
                   eq. (constant_coeff_helm)).
+* ``mixed``     - leaves of different orders in one problem (Sec. 2: p from a
+                  fixed set): edge unknowns at the lower order's nodes,
+                  interpolation of traces and fluxes (a reading), the
+                  reduced system, its solve and the full system;
 * ``interface`` - the reduced system on the leaf edges (eq. (hps_reduced)),
                   its sparse direct solve (Sec. 3.1: SciPy SuperLU with the
                   COLAMD ordering), the full unreduced collocation system for

@@ -209,6 +209,102 @@ def curved(p: int = 16, n: int = 8, kappa: float = 20.0, theta: float = 0.6,
     )
 
 
+@dataclass
+class MixedProblem:
+    """One boundary value problem on a rectangle of nx*ny equal leaves whose
+    orders p come from a fixed set (Sec. 2: p chosen per leaf from a few
+    values, as in hp-adaptivity); ``orders[t]`` is the p of leaf
+    t = ix + nx*iy.  Fields as in Problem."""
+
+    name: str
+    nx: int
+    ny: int
+    orders: np.ndarray
+    kappa: float
+    domain: tuple = (0.0, 1.0, 0.0, 1.0)
+    coef: Dict[str, CoefFn] = field(default_factory=dict)
+    g: Optional[CoefFn] = None
+    exact: Optional[CoefFn] = None
+    f: Optional[CoefFn] = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nleaf(self) -> int:
+        return self.nx * self.ny
+
+    def boxes(self) -> np.ndarray:
+        return Problem.boxes(self)
+
+    def sample(self, name: str, x, y, xp=np):
+        return Problem.sample(self, name, x, y, xp)
+
+    def has(self, name: str) -> bool:
+        return name in self.coef
+
+    def groups(self) -> List["LeafSet"]:
+        """One leaf set per order, orders ascending."""
+        orders = np.asarray(self.orders)
+        return [LeafSet(self, int(p), np.flatnonzero(orders == p)) for p in np.unique(orders)]
+
+
+@dataclass
+class LeafSet:
+    """The leaves of one order of a MixedProblem: a group of the leaf batch
+    (it answers the questions the batch asks of a Problem)."""
+
+    parent: MixedProblem
+    p: int
+    leaves: np.ndarray
+
+    @property
+    def name(self) -> str:
+        return f"{self.parent.name}_p{self.p}"
+
+    @property
+    def nleaf(self) -> int:
+        return int(self.leaves.size)
+
+    @property
+    def f(self):
+        return self.parent.f
+
+    def boxes(self) -> np.ndarray:
+        return self.parent.boxes()[self.leaves]
+
+    def sample(self, name: str, x, y, xp=np):
+        return self.parent.sample(name, x, y, xp)
+
+    def has(self, name: str) -> bool:
+        return self.parent.has(name)
+
+
+def mixed_tiny(n: int = 4, orders=(8, 12), kappa: float = 10.0) -> MixedProblem:
+    """The tiny workload's exact solution sin(kappa x1) on n x n leaves whose
+    orders alternate in a checkerboard over `orders`."""
+    sol = lambda x, y, xp: xp.sin(kappa * x)
+    o = np.array([orders[(ix + iy) % len(orders)] for iy in range(n) for ix in range(n)])
+    return MixedProblem(name=f"mixed_tiny_{n}x{n}_p{'-'.join(map(str, orders))}", nx=n, ny=n,
+                        orders=o, kappa=kappa, coef={"k2b": _const(kappa * kappa)}, g=sol,
+                        exact=sol, meta={"b": "1", "orders": list(orders)})
+
+
+def mixed_bump(n: int = 32, orders=(12, 20, 28), kappa: float = 150.0) -> MixedProblem:
+    """hp-style orders on one bump: b = 1 - 0.5 exp(-|x - (0.5, 0.5)|^2 / 0.02);
+    leaves whose centre lies within 0.15 of the bump's centre take the highest
+    order, within 0.3 the middle one, the rest the lowest.  g = cos(kappa x1)."""
+    b = gaussian_bumps_b([(0.5, 0.5)], 0.5, 0.02)
+    o = np.empty(n * n, dtype=np.int64)
+    h = 1.0 / n
+    for iy in range(n):
+        for ix in range(n):
+            r = math.hypot((ix + 0.5) * h - 0.5, (iy + 0.5) * h - 0.5)
+            o[ix + n * iy] = orders[2] if r < 0.15 else (orders[1] if r < 0.3 else orders[0])
+    return MixedProblem(name=f"mixed_bump_{n}x{n}", nx=n, ny=n, orders=o, kappa=kappa,
+                        coef={"k2b": _scaled(kappa, b)},
+                        g=lambda x, y, xp: xp.cos(kappa * x),
+                        meta={"b": "1-0.5*exp(-|x-(.5,.5)|^2/0.02)", "orders": list(orders)})
+
+
 UNEVEN_P = (8, 12, 16, 20, 24, 28, 30, 32)
 
 
