@@ -52,6 +52,8 @@ WORKLOADS = {
     "annulus": ("annulus", "quarter annulus 128x16 leaves p=20 kappa=150"),
     "uneven": ("uneven_batch", "eight problems p=8..32 in one batch"),
     "tiny": ("tiny", "4x4 leaves p=8 kappa=10"),
+    "mixed": ("mixed_bump", "32x32 leaves of orders 12 / 20 / 28 (one problem, by distance to a "
+                            "bump), kappa=150"),
     "curved": ("curved", "the paper's curved domain (mixed term a12), 48x48 leaves p=20 kappa=150",
                {"p": 20, "n": 48, "kappa": 150.0}),
 }
@@ -90,6 +92,8 @@ def make_problems(workload: str):
     from paper_2211_14969_amd import inputs
     entry = WORKLOADS[workload]
     made = getattr(inputs, entry[0])(**(entry[2] if len(entry) > 2 else {}))
+    if hasattr(made, "groups"):      # one problem, leaves of several orders
+        return made.groups()
     return made if isinstance(made, list) else [made]
 
 
@@ -321,17 +325,17 @@ def recover_timing(B, steps: int):
                               "precision": "fp64"}}
 
 
-def iface_timing(B, prec, max_refine: int, steps: int):
+def iface_timing(B, prob, prec, max_refine: int, steps: int):
     """Time the FP64 interface solve (nested dissection on the device) of a
-    single-problem batch: the factorisation from the leaves' S and one solve
+    single-problem batch (one group, or one group per order of a problem
+    with mixed orders): the factorisation from the leaves' S and one solve
     for u_b.  Not part of the condensation step."""
     import torch
-    from paper_2211_14969_amd import hps
-    from paper_2211_14969_amd.harness import InterfaceSolver, dirichlet_data
-    prob = B.groups[0].problem
+    from paper_2211_14969_amd.harness import (InterfaceSolver, dirichlet_data_batch,
+                                              interface_unknowns)
     S, w, _, _ = B.condense(prec=prec, max_refine=max_refine, sync=True)
-    g = dirichlet_data(B.groups[0])
-    it = InterfaceSolver(B.ctx, prob)
+    g = dirichlet_data_batch(B)
+    it = InterfaceSolver(B.ctx, prob, B)
     ub = torch.empty_like(w)
     it.factor(S, sync=True)
     it.solve(S, w, g, ub, sync=True)
@@ -348,8 +352,7 @@ def iface_timing(B, prec, max_refine: int, steps: int):
     plan = it.plan
     it.close()
     tf = plan["factor_flop"] / (out["factor"] * 1e-3) / 1e12
-    m = prob.p - 2
-    return {"unknowns": ((prob.nx - 1) * prob.ny + prob.nx * (prob.ny - 1)) * m,
+    return {"unknowns": interface_unknowns(prob),
             "fronts": plan["fronts"], "levels": plan["levels"],
             "max_separator": plan["max_separator"], "factor_ms": out["factor"],
             "solve_ms": out["solve"], "factor_flop": plan["factor_flop"],
@@ -440,7 +443,9 @@ def main() -> int:
     fl = {k: sum(algorithmic_flops(q.p)[k] * q.nleaf for q in probs) / L
           for k in ("factor", "backsolve", "schur", "total")}
     value = L / (ms * 1e-3)
-    workload_name = prob.name if len(probs) == 1 else "uneven_8_problems"
+    parent = getattr(prob, "parent", None)    # the problem of a mixed-order batch
+    workload_name = (prob.name if len(probs) == 1 else
+                     parent.name if parent is not None else "uneven_8_problems")
     line = {
         "metric": "leaf condensations/s + % MFMA peak; FP64 vs FP32+refine at <=1e-9 rel err",
         "value": value,
@@ -512,10 +517,10 @@ def main() -> int:
         B.condense(prec=prec, max_refine=args.max_refine, sync=True)
         line["recover"] = recover_timing(B, max(3, args.steps // 2))
 
-    if not args.no_iface and len(probs) == 1:
+    if not args.no_iface and (len(probs) == 1 or parent is not None):
         try:
-            line["interface_solve"] = iface_timing(B, prec, args.max_refine,
-                                                   max(3, args.steps // 4))
+            line["interface_solve"] = iface_timing(B, parent if parent is not None else prob,
+                                                   prec, args.max_refine, max(3, args.steps // 4))
             print("# timed the interface solve", file=sys.stderr, flush=True)
         except hps.HpsError as e:   # e.g. a separator above the build's limit
             line["interface_solve"] = {"skipped": str(e)}

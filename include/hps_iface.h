@@ -23,10 +23,12 @@
  * multi-column triangular solve and the Schur-complement update (FP64 MFMA).
  * Pivoting is within each separator block (no exchanges between fronts).
  *
- * Grid and layouts: one problem on an nx x ny grid of equal leaves of order
- * p, leaf t = ix + nx*iy (ix along x1); each leaf's S is [nb][nb] and w, g
- * and u_b are [nb] in the boundary order of hps_leaf.h (W, E, S, N, each
- * p-2 nodes in increasing coordinate), leaves concatenated in leaf order.
+ * Grid and layouts: one problem on an nx x ny grid of equal leaves, leaf
+ * t = ix + nx*iy (ix along x1), all of order p (hps_iface_create) or each
+ * of its own order (hps_iface_create_orders); each leaf's S is [nb][nb]
+ * and w, g and u_b are [nb] in the boundary order of hps_leaf.h (W, E, S,
+ * N, each p-2 nodes in increasing coordinate), leaves concatenated in leaf
+ * order unless offsets are given.
  * All arrays are caller-owned DEVICE memory and must stay valid until the
  * context stream has executed the call; calls are asynchronous on the
  * context stream.  Argument errors are returned synchronously and nothing
@@ -55,6 +57,16 @@ typedef struct hps_iface hps_iface;
 hps_status hps_iface_plan(int p, int nx, int ny, int *nfront, int *levels, int *max_sep,
                           double *factor_flop, size_t *bytes);
 
+/* Host-only planning of a grid whose leaves differ in order (Sec. 2: p
+ * chosen per leaf from a fixed set).  orders: host [nx*ny], the p of leaf
+ * t = ix + nx*iy.  A shared edge carries the nodes of the lower of its two
+ * leaves' orders; the other leaf's trace is the polynomial through them,
+ * evaluated at its own edge nodes, and its flux is carried back to the
+ * edge's nodes by the polynomial through its nodal fluxes (the fluxes
+ * balance there).  Outputs and errors as hps_iface_plan. */
+hps_status hps_iface_plan_orders(int nx, int ny, const int *orders, int *nfront, int *levels,
+                                 int *max_sep, double *factor_flop, size_t *bytes);
+
 /* Host-only: per-front sizes of that plan, in the order the fronts are
  * factored (by tree level, leaves' parents first): separator nodes nS,
  * exterior nodes nE and tree level of each front; arrays of nfront entries
@@ -65,6 +77,17 @@ hps_status hps_iface_plan_fronts(int p, int nx, int ny, int *nS, int *nE, int *l
  * Schur complements, sized by hps_iface_plan's `bytes`).  Errors as
  * hps_iface_plan, plus HPS_ERR_OOM / HPS_ERR_HIP. */
 hps_status hps_iface_create(hps_ctx *ctx, int p, int nx, int ny, hps_iface **out);
+
+/* As hps_iface_create for leaves of different orders (orders: host
+ * [nx*ny], as in hps_iface_plan_orders).  s_off / b_off: host [nx*ny], the
+ * offset (in doubles) of leaf t's S [nb_t][nb_t] in the S array, and of its
+ * nb_t boundary slots in the w, g and ub arrays, nb_t = 4(p_t - 2) (the
+ * layout of a leaf batch with one group per order: groups concatenated);
+ * NULL for leaf-major order.  Leaves on an edge of lower order on their
+ * other side have their S taken to the edge basis at factorisation time. */
+hps_status hps_iface_create_orders(hps_ctx *ctx, int nx, int ny, const int *orders,
+                                   const long long *s_off, const long long *b_off,
+                                   hps_iface **out);
 
 /* Factorisation (the build of Sec. 2's direct solver) from the leaves' maps
  * S [nx*ny][nb][nb].  Per front it keeps the LU factors of the separator

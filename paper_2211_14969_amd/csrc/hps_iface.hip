@@ -6,8 +6,16 @@
 // boundary (nodes on the outer boundary carry Dirichlet data and are never
 // unknowns).  Bisecting box b into halves a and c, the separator s is the
 // set of nodes both halves have on their boundary (the leaf edges along the
-// cut), and E_b = (E_a \ s) ++ (E_c \ s).  A leaf's exterior lists its unknown
-// boundary slots, and its Schur complement is its own S restricted to them.
+// cut), and E_b = (E_a \ s) ++ (E_c \ s).  A leaf's exterior lists its
+// unknown edge nodes, and its Schur complement is its own S restricted to
+// them.
+//
+// Leaves may differ in order (Sec. 2: p from a fixed set).  A shared edge
+// then carries the nodes of its lower-order leaf; the other leaf sees the
+// polynomial through them at its own nodes (P) and returns its flux through
+// the polynomial through its own values (R), so its Schur complement in the
+// edge basis is R S P (k_nd_leaf_transform) and its right-hand side R r.
+// With one order everywhere no leaf is transformed.
 //
 // Factorisation (device), level by level from the leaves up; the fronts of
 // one level are independent and run as one batch:
@@ -26,8 +34,10 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <map>
 #include <new>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/hps_iface.h"
@@ -41,14 +51,15 @@ constexpr int kMaxSep = HPS_IFACE_MAX_SEPARATOR;
 constexpr int kFactorThreads = 512;   // LU of one separator block per workgroup
 constexpr int kSolveThreads = 512;    // 16 right-hand sides per workgroup
 
-// One front as the kernels see it.  Arena offsets are in doubles (FP64
-// arena) or ints (int arena).  A child that is a leaf is coded as -(leaf+1):
-// its Schur complement is S + leaf*nb*nb (leading dimension nb) and its
-// reduced right-hand side the leaf's row of the leaf right-hand sides.
+// One front as the kernels see it.  Offsets are in doubles or ints.  A
+// child's Schur complement and reduced right-hand side live in the FP64
+// arena (kind 0: a front, or a transformed leaf) or in the caller's S and
+// the leaf right-hand sides (kind 1: a leaf taken as it is).
 struct Front {
   long long fss, x, fes, t, y, r;
   long long ca, cc;   // children's Schur complements
   long long ra, rc;   // children's reduced right-hand sides
+  int ka, kc;         // kinds of the two children
   int lda, ldc;       // leading dimensions of the children's Schur complements
   int map;            // int arena: map_a [nS+nE], then map_c [nS+nE]
   int gid;            // int arena: global node ids, separator then exterior
@@ -56,50 +67,56 @@ struct Front {
   int nS, nE;
 };
 
-// Global id of slot s of leaf t, and whether it lies on the outer boundary.
-// Edge ids: vertical edges (line ix = 0..nx, row iy) first, then horizontal
-// ones (column ix, line iy = 0..ny); node k of an edge is id * m + k.
-__host__ __device__ inline int leaf_node(int nx, int ny, int m, int t, int s, bool &dir) {
-  const int ix = t % nx, iy = t / nx;
-  const int side = s / m, k = s - side * m;
-  const int nv = (nx + 1) * ny;
-  int e;
-  if (side == 0) {
-    e = ix + (nx + 1) * iy;
-    dir = ix == 0;
-  } else if (side == 1) {
-    e = ix + 1 + (nx + 1) * iy;
-    dir = ix + 1 == nx;
-  } else if (side == 2) {
-    e = nv + ix + nx * iy;
-    dir = iy == 0;
-  } else {
-    e = nv + ix + nx * (iy + 1);
-    dir = iy + 1 == ny;
-  }
-  return e * m + k;
-}
+// One side of a leaf: the first global node of its edge and the edge's node
+// count; P [m][me] and R [me][m] are offsets into the interpolation table,
+// -1 where the edge carries the leaf's own nodes.
+struct Side {
+  int node0, me, P, R, dir;
+};
+
+struct LeafD {
+  long long s_off, b_off;   // the leaf's S and boundary slots in the caller's arrays
+  long long t_off, r_off;   // transformed leaves: R S P [ne][ne] and R r [ne] in the arena
+  int m, ne;                // nodes per side; unknowns of its interface sides (edge basis)
+  Side side[4];             // W, E, S, N
+};
 
 __device__ __forceinline__ d4 mma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ const double *child_T(const Front &f, bool first, const double *ar,
-                                                 const double *S, int nb) {
-  const long long o = first ? f.ca : f.cc;
-  return o < 0 ? S + (size_t)(-o - 1) * nb * nb : ar + o;
+                                                 const double *S) {
+  return ((first ? f.ka : f.kc) ? S : ar) + (first ? f.ca : f.cc);
+}
+
+__device__ __forceinline__ const double *child_r(const Front &f, bool first, const double *ar,
+                                                 const double *rl) {
+  return ((first ? f.ka : f.kc) ? rl : ar) + (first ? f.ra : f.rc);
+}
+
+// Side and index of column c of a transformed leaf's edge basis (its
+// interface sides in the order W, E, S, N).
+__device__ __forceinline__ void edge_basis(const LeafD &L, int c, int &s, int &i) {
+  s = 0;
+  for (; s < 4; ++s) {
+    if (L.side[s].dir) continue;
+    if (c < L.side[s].me) break;
+    c -= L.side[s].me;
+  }
+  i = c;
 }
 
 // ---------------------------------------------------------------------------
 // assembly of the fronts of one level: F = T_a (+) T_c
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_nd_front(const Front *fr, int first, double *ar,
-                                                  const int *ia, const double *S, int nb) {
+                                                  const int *ia, const double *S) {
   const Front f = fr[first + blockIdx.y];
   const int nS = f.nS, nE = f.nE, n = nS + nE;
   const long long tot = (long long)n * n;
-  const double *Ta = child_T(f, true, ar, S, nb);
-  const double *Tc = child_T(f, false, ar, S, nb);
+  const double *Ta = child_T(f, true, ar, S);
+  const double *Tc = child_T(f, false, ar, S);
   const int *ma = ia + f.map, *mc = ma + n;
   for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < tot;
        e += (long long)gridDim.x * 256) {
@@ -115,6 +132,49 @@ __global__ __launch_bounds__(256) void k_nd_front(const Front *fr, int first, do
       if (j < nS) ar[f.fes + (size_t)(i - nS) * nS + j] = v;
       else ar[f.t + (size_t)(i - nS) * nE + (j - nS)] = v;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// leaves on an order boundary: their Schur complement in the edge basis,
+// T = R S P over their interface sides (U = S P staged in LDS)
+// ---------------------------------------------------------------------------
+size_t transform_lds(int m, int ne) { return sizeof(double) * (size_t)(4 * m) * ne; }
+
+__global__ __launch_bounds__(256) void k_nd_leaf_transform(const LeafD *ld, const int *tlist,
+                                                           const double *S, const double *tab,
+                                                           double *ar) {
+  extern __shared__ double U[];   // [nb][ne]
+  const LeafD &L = ld[tlist[blockIdx.x]];
+  const int m = L.m, nb = 4 * m, ne = L.ne;
+  const double *Sl = S + L.s_off;
+  for (int e = threadIdx.x; e < nb * ne; e += 256) {
+    const int r = e / ne, c = e - r * ne;
+    int q, j;
+    edge_basis(L, c, q, j);
+    const Side sd = L.side[q];
+    const double *row = Sl + (size_t)r * nb + q * m;
+    double v = 0.0;
+    if (sd.P < 0) {
+      v = row[j];
+    } else {
+      for (int l = 0; l < m; ++l) v += row[l] * tab[sd.P + l * sd.me + j];
+    }
+    U[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ne * ne; e += 256) {
+    const int a = e / ne, c = e - a * ne;
+    int s, i;
+    edge_basis(L, a, s, i);
+    const Side sd = L.side[s];
+    double v = 0.0;
+    if (sd.R < 0) {
+      v = U[(s * m + i) * ne + c];
+    } else {
+      for (int k = 0; k < m; ++k) v += tab[sd.R + i * m + k] * U[(s * m + k) * ne + c];
+    }
+    ar[L.t_off + e] = v;
   }
 }
 
@@ -467,44 +527,54 @@ __global__ __launch_bounds__(256) void k_nd_gemm(const Front *fr, int first, dou
 // ---------------------------------------------------------------------------
 // solve phase
 // ---------------------------------------------------------------------------
-// r_t = -(w_t + S_t[:, D] g_D) at every slot of every leaf (the Dirichlet
-// slots' own entries are never read)
-__global__ void k_nd_leaf_rhs(int L, int nx, int ny, int m, const double *S, const double *w,
-                              const double *g, double *rl) {
-  const int nb = 4 * m;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)L * nb) return;
-  const int t = (int)(i / nb), s = (int)(i - (size_t)t * nb);
-  bool dir;
-  leaf_node(nx, ny, m, t, s, dir);
-  double v = w ? w[i] : 0.0;
-  if (!dir) {
-    const double *row = S + ((size_t)t * nb + s) * nb;
-    const double *gt = g + (size_t)t * nb;
-    for (int side = 0; side < 4; ++side) {
-      bool d;
-      leaf_node(nx, ny, m, t, side * m, d);
-      if (!d) continue;
-      for (int k = side * m; k < side * m + m; ++k) v += row[k] * gt[k];
+// r_t = -(w_t + S_t[:, D] g_D) at the slots of the leaf's interface sides
+// (the Dirichlet slots are never read); a transformed leaf stores R r_t in
+// its edge basis.  One workgroup per leaf.
+__global__ __launch_bounds__(128) void k_nd_leaf_rhs(const LeafD *ld, const double *S,
+                                                     const double *w, const double *g,
+                                                     const double *tab, double *rl, double *ar) {
+  __shared__ double rf[4 * HPS_P_MAX];
+  const LeafD &L = ld[blockIdx.x];
+  const int m = L.m, nb = 4 * m;
+  for (int s = threadIdx.x; s < nb; s += 128) {
+    const int side = s / m;
+    double v = 0.0;
+    if (!L.side[side].dir) {
+      v = w ? w[L.b_off + s] : 0.0;
+      const double *row = S + L.s_off + (size_t)s * nb;
+      for (int d = 0; d < 4; ++d) {
+        if (!L.side[d].dir) continue;
+        for (int k = d * m; k < d * m + m; ++k) v += row[k] * g[L.b_off + k];
+      }
+      v = -v;
     }
+    if (L.t_off < 0) rl[L.b_off + s] = v;
+    else rf[s] = v;
   }
-  rl[i] = dir ? 0.0 : -v;
-}
-
-
-__device__ __forceinline__ const double *child_r(const Front &f, bool first, const double *ar,
-                                                 const double *rl, int nb) {
-  const long long o = first ? f.ra : f.rc;
-  return o < 0 ? rl + (size_t)(-o - 1) * nb : ar + o;
+  if (L.t_off < 0) return;
+  __syncthreads();
+  for (int a = threadIdx.x; a < L.ne; a += 128) {
+    int s, i;
+    edge_basis(L, a, s, i);
+    const Side sd = L.side[s];
+    double v;
+    if (sd.R < 0) {
+      v = rf[s * m + i];
+    } else {
+      v = 0.0;
+      for (int k = 0; k < m; ++k) v += tab[sd.R + i * m + k] * rf[s * m + k];
+    }
+    ar[L.r_off + a] = v;
+  }
 }
 
 // y = r_s and r_b = r_e, scattered from the halves' reduced right-hand sides
 __global__ __launch_bounds__(256) void k_nd_front_rhs(const Front *fr, int first, double *ar,
-                                                      const int *ia, const double *rl, int nb) {
+                                                      const int *ia, const double *rl) {
   const Front f = fr[first + blockIdx.x];
   const int n = f.nS + f.nE;
-  const double *ra = child_r(f, true, ar, rl, nb);
-  const double *rc = child_r(f, false, ar, rl, nb);
+  const double *ra = child_r(f, true, ar, rl);
+  const double *rc = child_r(f, false, ar, rl);
   const int *ma = ia + f.map, *mc = ma + n;
   for (int i = threadIdx.x; i < n; i += 256) {
     double v = 0.0;
@@ -515,7 +585,6 @@ __global__ __launch_bounds__(256) void k_nd_front_rhs(const Front *fr, int first
   }
 }
 
-// r_b -= F_es y, one wavefront per row
 __global__ __launch_bounds__(256) void k_nd_gemv_r(const Front *fr, int first, double *ar) {
   const Front f = fr[first + blockIdx.y];
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -543,31 +612,69 @@ __global__ __launch_bounds__(256) void k_nd_down(const Front *fr, int first, con
 }
 
 // ub: solved interface values, g on the outer boundary
-__global__ void k_nd_output(int L, int nx, int ny, int m, const double *u, const double *g,
-                            double *ub) {
-  const int nb = 4 * m;
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)L * nb) return;
-  const int t = (int)(i / nb), s = (int)(i - (size_t)t * nb);
-  bool dir;
-  const int node = leaf_node(nx, ny, m, t, s, dir);
-  ub[i] = dir ? g[i] : u[node];
+// ub: interface values (interpolated to the leaf's nodes where its edge
+// carries a lower order's nodes), g on the outer boundary.  One workgroup
+// per leaf.
+__global__ __launch_bounds__(128) void k_nd_output(const LeafD *ld, const double *u,
+                                                   const double *g, const double *tab,
+                                                   double *ub) {
+  const LeafD &L = ld[blockIdx.x];
+  const int m = L.m, nb = 4 * m;
+  for (int s = threadIdx.x; s < nb; s += 128) {
+    const int side = s / m, k = s - side * m;
+    const Side sd = L.side[side];
+    double v;
+    if (sd.dir) {
+      v = g[L.b_off + s];
+    } else if (sd.P < 0) {
+      v = u[sd.node0 + k];
+    } else {
+      v = 0.0;
+      for (int j = 0; j < sd.me; ++j) v += tab[sd.P + k * sd.me + j] * u[sd.node0 + j];
+    }
+    ub[L.b_off + s] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
 // host planning
 // ---------------------------------------------------------------------------
 struct Plan {
-  int p = 0, m = 0, nb = 0, nx = 0, ny = 0, L = 0;
+  int nx = 0, ny = 0, L = 0;
   std::vector<Front> fronts;      // ordered by level
   std::vector<int> level_first;   // fronts of level l: [level_first[l], level_first[l+1])
   std::vector<int> level_max_s, level_max_e;
   std::vector<int> ints;          // int arena (maps, node ids; pivot orders left 0)
+  std::vector<LeafD> leaves;
+  std::vector<int> tlist;         // leaves taken to the edge basis
+  int t_max_m = 0, t_max_ne = 0;
+  std::vector<double> tab;        // interpolation matrices
   size_t ndouble = 0;
+  size_t nslot = 0;               // extent of the slot arrays (w, g, ub)
   int max_sep = 0;
   double flop = 0.0;
   int nnode = 0;                  // edge nodes of the grid (Dirichlet included)
 };
+
+// M [m_to][m_from]: values at the interior Chebyshev extreme points of order
+// m_to + 2 of the polynomial through values at those of order m_from + 2.
+void interp_matrix(int m_from, int m_to, double *M) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  auto pts = [&](int m) {
+    std::vector<long double> t(m);
+    const int n = m + 1;
+    for (int k = 1; k <= m; ++k) t[k - 1] = std::sin(pi * (long double)(2 * k - n) / (2.0L * n));
+    return t;
+  };
+  const std::vector<long double> s = pts(m_from), t = pts(m_to);
+  for (int i = 0; i < m_to; ++i)
+    for (int k = 0; k < m_from; ++k) {
+      long double v = 1.0L;
+      for (int q = 0; q < m_from; ++q)
+        if (q != k) v *= (t[i] - s[q]) / (s[k] - s[q]);
+      M[(size_t)i * m_from + k] = (double)v;
+    }
+}
 
 struct BoxOut {
   int front = -1;              // -1: a leaf
@@ -584,7 +691,8 @@ struct FrontH {
 };
 
 struct Planner {
-  int nx, ny, m;
+  int nx, ny;
+  const std::vector<LeafD> *leaves;
   std::vector<FrontH> fronts;
   int max_sep = 0;
 
@@ -592,12 +700,16 @@ struct Planner {
     BoxOut out;
     if (x1 - x0 == 1 && y1 - y0 == 1) {
       out.leaf = x0 + nx * y0;
-      for (int s = 0; s < 4 * m; ++s) {
-        bool dir;
-        const int node = leaf_node(nx, ny, m, out.leaf, s, dir);
-        if (dir) continue;
-        out.E.push_back(node);
-        out.pos.push_back(s);
+      const LeafD &L = (*leaves)[out.leaf];
+      int run = 0;
+      for (int s = 0; s < 4; ++s) {
+        const Side &sd = L.side[s];
+        if (sd.dir) continue;
+        for (int k = 0; k < sd.me; ++k) {
+          out.E.push_back(sd.node0 + k);
+          out.pos.push_back(L.t_off >= 0 ? run + k : s * L.m + k);
+        }
+        run += sd.me;
       }
       return out;
     }
@@ -666,17 +778,98 @@ struct Planner {
   }
 };
 
-hps_status make_plan(int p, int nx, int ny, Plan &pl) {
-  if (p < HPS_P_MIN || p > HPS_P_MAX || nx < 1 || ny < 1) return HPS_ERR_INVALID;
+auto align32 = [](size_t v) { return (v + 31) & ~(size_t)31; };
+
+// Edges of the grid (vertical: line ix = 0..nx, row iy; then horizontal:
+// column ix, line iy = 0..ny), their node counts (the lower order of the two
+// leaves that share it; an outer edge keeps its leaf's), the leaves' sides
+// and interpolations.  Offsets s_off / b_off (may be null: leaf-major with
+// one order) place each leaf's S and slots in the caller's arrays.
+hps_status make_leaves(int nx, int ny, const int *orders, const long long *s_off,
+                       const long long *b_off, Plan &pl) {
+  const int L = nx * ny;
+  const int nv = (nx + 1) * ny, nedge = nv + nx * (ny + 1);
+  std::vector<int> me(nedge, INT_MAX), owners(nedge, 0);
+  auto edges_of = [&](int t, int e[4]) {
+    const int ix = t % nx, iy = t / nx;
+    e[0] = ix + (nx + 1) * iy;
+    e[1] = ix + 1 + (nx + 1) * iy;
+    e[2] = nv + ix + nx * iy;
+    e[3] = nv + ix + nx * (iy + 1);
+  };
+  for (int t = 0; t < L; ++t) {
+    if (orders[t] < HPS_P_MIN || orders[t] > HPS_P_MAX) return HPS_ERR_INVALID;
+    if ((s_off && s_off[t] < 0) || (b_off && b_off[t] < 0)) return HPS_ERR_INVALID;
+    int e[4];
+    edges_of(t, e);
+    for (int s = 0; s < 4; ++s) {
+      me[e[s]] = std::min(me[e[s]], orders[t] - 2);
+      owners[e[s]]++;
+    }
+  }
+  std::vector<int> node0(nedge + 1, 0);
+  for (int e = 0; e < nedge; ++e) node0[e + 1] = node0[e] + me[e];
+  pl.nnode = node0[nedge];
+  std::map<std::pair<int, int>, int> tabs;   // (m_from, m_to) -> offset
+  auto table = [&](int m_from, int m_to) {
+    auto it = tabs.find({m_from, m_to});
+    if (it != tabs.end()) return it->second;
+    const int off = (int)pl.tab.size();
+    pl.tab.resize(pl.tab.size() + (size_t)m_from * m_to);
+    interp_matrix(m_from, m_to, pl.tab.data() + off);
+    tabs[{m_from, m_to}] = off;
+    return off;
+  };
+  pl.leaves.assign(L, LeafD{});
+  long long s_run = 0, b_run = 0;
+  for (int t = 0; t < L; ++t) {
+    LeafD &d = pl.leaves[t];
+    d.m = orders[t] - 2;
+    const int nb = 4 * d.m;
+    d.s_off = s_off ? s_off[t] : s_run;
+    d.b_off = b_off ? b_off[t] : b_run;
+    s_run += (long long)nb * nb;
+    b_run += nb;
+    pl.nslot = std::max(pl.nslot, (size_t)(d.b_off + nb));
+    int e[4];
+    edges_of(t, e);
+    d.ne = 0;
+    bool transformed = false;
+    for (int s = 0; s < 4; ++s) {
+      Side &sd = d.side[s];
+      sd.node0 = node0[e[s]];
+      sd.me = me[e[s]];
+      sd.dir = owners[e[s]] == 1;
+      sd.P = sd.R = -1;
+      if (!sd.dir) {
+        d.ne += sd.me;
+        if (sd.me < d.m) {
+          transformed = true;
+          sd.P = table(sd.me, d.m);   // [m][me]
+          sd.R = table(d.m, sd.me);   // [me][m]
+        }
+      }
+    }
+    d.t_off = d.r_off = transformed ? 0 : -1;
+    if (transformed) {
+      pl.tlist.push_back(t);
+      pl.t_max_m = std::max(pl.t_max_m, d.m);
+      pl.t_max_ne = std::max(pl.t_max_ne, d.ne);
+    }
+  }
+  return HPS_OK;
+}
+
+hps_status make_plan(int nx, int ny, const int *orders, const long long *s_off,
+                     const long long *b_off, Plan &pl) {
+  if (!orders || nx < 1 || ny < 1) return HPS_ERR_INVALID;
   if ((long long)nx * ny > (1 << 22)) return HPS_ERR_INVALID;
-  pl.p = p;
-  pl.m = p - 2;
-  pl.nb = 4 * pl.m;
   pl.nx = nx;
   pl.ny = ny;
   pl.L = nx * ny;
-  pl.nnode = ((nx + 1) * ny + nx * (ny + 1)) * pl.m;
-  Planner P{nx, ny, pl.m, {}, 0};
+  const hps_status st = make_leaves(nx, ny, orders, s_off, b_off, pl);
+  if (st != HPS_OK) return st;
+  Planner P{nx, ny, &pl.leaves, {}, 0};
   P.build(0, nx, 0, ny);
   pl.max_sep = P.max_sep;
   if (P.max_sep > kMaxSep) return HPS_ERR_INVALID;
@@ -693,7 +886,6 @@ hps_status make_plan(int p, int nx, int ny, Plan &pl) {
   pl.level_first.assign(nlev + 2, nf);
   pl.level_max_s.assign(nlev + 1, 0);
   pl.level_max_e.assign(nlev + 1, 0);
-  auto align = [](size_t v) { return (v + 31) & ~(size_t)31; };
   size_t od = 0;
   // level_first[l]: first front (in level order) whose level is at least l
   for (int l = 1, k = 0; l <= nlev + 1; ++l) {
@@ -706,12 +898,12 @@ hps_status make_plan(int p, int nx, int ny, Plan &pl) {
     const size_t s = h.nS, e = h.nE;
     f.nS = h.nS;
     f.nE = h.nE;
-    f.fss = (long long)od; od = align(od + s * s);
-    f.x = (long long)od;   od = align(od + s * e);
-    f.fes = (long long)od; od = align(od + e * s);
-    f.t = (long long)od;   od = align(od + e * e);
-    f.y = (long long)od;   od = align(od + s);
-    f.r = (long long)od;   od = align(od + e);
+    f.fss = (long long)od; od = align32(od + s * s);
+    f.x = (long long)od;   od = align32(od + s * e);
+    f.fes = (long long)od; od = align32(od + e * s);
+    f.t = (long long)od;   od = align32(od + e * e);
+    f.y = (long long)od;   od = align32(od + s);
+    f.r = (long long)od;   od = align32(od + e);
     f.map = (int)pl.ints.size();
     pl.ints.insert(pl.ints.end(), h.map_a.begin(), h.map_a.end());
     pl.ints.insert(pl.ints.end(), h.map_c.begin(), h.map_c.end());
@@ -723,27 +915,50 @@ hps_status make_plan(int p, int nx, int ny, Plan &pl) {
     pl.level_max_e[h.level] = std::max(pl.level_max_e[h.level], h.nE);
     pl.flop += (2.0 / 3.0) * s * s * s + 2.0 * s * s * e + 2.0 * e * e * s;
   }
-  // children: leaves by code, fronts by their (reordered) arena offsets
+  // transformed leaves: R S P and R r in the arena
+  for (int t : pl.tlist) {
+    LeafD &d = pl.leaves[t];
+    d.t_off = (long long)od; od = align32(od + (size_t)d.ne * d.ne);
+    d.r_off = (long long)od; od = align32(od + (size_t)d.ne);
+  }
+  // children: fronts and transformed leaves in the arena, other leaves in S
   for (int k = 0; k < nf; ++k) {
     const FrontH &h = P.fronts[order[k]];
     Front &f = pl.fronts[k];
-    auto child = [&](int c, long long &tOff, long long &rOff, int &ld) {
+    auto child = [&](int c, long long &tOff, long long &rOff, int &kind, int &ld) {
       if (c < 0) {
-        tOff = c;
-        rOff = c;
-        ld = pl.nb;
+        const LeafD &d = pl.leaves[-c - 1];
+        if (d.t_off >= 0) {
+          kind = 0;
+          tOff = d.t_off;
+          rOff = d.r_off;
+          ld = d.ne;
+        } else {
+          kind = 1;
+          tOff = d.s_off;
+          rOff = d.b_off;
+          ld = 4 * d.m;
+        }
       } else {
         const Front &cf = pl.fronts[where[c]];
+        kind = 0;
         tOff = cf.t;
         rOff = cf.r;
         ld = cf.nE;
       }
     };
-    child(h.childA, f.ca, f.ra, f.lda);
-    child(h.childC, f.cc, f.rc, f.ldc);
+    child(h.childA, f.ca, f.ra, f.ka, f.lda);
+    child(h.childC, f.cc, f.rc, f.kc, f.ldc);
   }
   pl.ndouble = od;
   return HPS_OK;
+}
+
+size_t plan_bytes(const Plan &pl) {
+  return pl.ndouble * sizeof(double) + pl.ints.size() * sizeof(int) +
+         pl.fronts.size() * (sizeof(Front) + sizeof(int)) + pl.leaves.size() * sizeof(LeafD) +
+         pl.tlist.size() * sizeof(int) + pl.tab.size() * sizeof(double) +
+         (pl.nslot + (size_t)pl.nnode) * sizeof(double);
 }
 
 template <typename K>
@@ -764,43 +979,69 @@ struct hps_iface {
   hipStream_t stream = nullptr;
   Plan plan;
   Front *d_front = nullptr;
+  LeafD *d_leaf = nullptr;
+  int *d_tlist = nullptr;
+  double *d_tab = nullptr;
   double *d_ar = nullptr;
   int *d_ia = nullptr;
   int *d_info = nullptr;
-  double *d_rl = nullptr;   // leaf right-hand sides [L][nb]
+  double *d_rl = nullptr;   // leaf right-hand sides, in the slot layout
   double *d_u = nullptr;    // every edge node's value
 };
+
+namespace {
+
+hps_status plan_checked(int nx, int ny, const int *orders, const long long *s_off,
+                        const long long *b_off, Plan &pl) {
+  try {
+    return make_plan(nx, ny, orders, s_off, b_off, pl);
+  } catch (...) {
+    return HPS_ERR_OOM;
+  }
+}
+
+std::vector<int> uniform_orders(int p, int nx, int ny) {
+  return std::vector<int>((size_t)std::max(nx, 0) * std::max(ny, 0), p);
+}
+
+hps_status report(const Plan &pl, int *nfront, int *levels, int *max_sep, double *factor_flop,
+                  size_t *bytes) {
+  if (nfront) *nfront = (int)pl.fronts.size();
+  if (levels) *levels = (int)pl.level_first.size() - 2;
+  if (max_sep) *max_sep = pl.max_sep;
+  if (factor_flop) *factor_flop = pl.flop;
+  if (bytes) *bytes = plan_bytes(pl);
+  return HPS_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
 hps_status hps_iface_plan(int p, int nx, int ny, int *nfront, int *levels, int *max_sep,
                           double *factor_flop, size_t *bytes) {
+  if (nx < 1 || ny < 1) return HPS_ERR_INVALID;
   Plan pl;
-  try {
-    const hps_status st = make_plan(p, nx, ny, pl);
-    if (st != HPS_OK) return st;
-  } catch (...) {
-    return HPS_ERR_OOM;
-  }
-  if (nfront) *nfront = (int)pl.fronts.size();
-  if (levels) *levels = (int)pl.level_first.size() - 2;
-  if (max_sep) *max_sep = pl.max_sep;
-  if (factor_flop) *factor_flop = pl.flop;
-  if (bytes)
-    *bytes = pl.ndouble * sizeof(double) + pl.ints.size() * sizeof(int) +
-             pl.fronts.size() * (sizeof(Front) + sizeof(int)) +
-             ((size_t)pl.L * pl.nb + pl.nnode) * sizeof(double);
-  return HPS_OK;
+  const std::vector<int> o = uniform_orders(p, nx, ny);
+  const hps_status st = plan_checked(nx, ny, o.data(), nullptr, nullptr, pl);
+  if (st != HPS_OK) return st;
+  return report(pl, nfront, levels, max_sep, factor_flop, bytes);
+}
+
+hps_status hps_iface_plan_orders(int nx, int ny, const int *orders, int *nfront, int *levels,
+                                 int *max_sep, double *factor_flop, size_t *bytes) {
+  Plan pl;
+  const hps_status st = plan_checked(nx, ny, orders, nullptr, nullptr, pl);
+  if (st != HPS_OK) return st;
+  return report(pl, nfront, levels, max_sep, factor_flop, bytes);
 }
 
 hps_status hps_iface_plan_fronts(int p, int nx, int ny, int *nS, int *nE, int *level) {
+  if (nx < 1 || ny < 1) return HPS_ERR_INVALID;
   Plan pl;
-  try {
-    const hps_status st = make_plan(p, nx, ny, pl);
-    if (st != HPS_OK) return st;
-  } catch (...) {
-    return HPS_ERR_OOM;
-  }
+  const std::vector<int> o = uniform_orders(p, nx, ny);
+  const hps_status st = plan_checked(nx, ny, o.data(), nullptr, nullptr, pl);
+  if (st != HPS_OK) return st;
   const int nlev = (int)pl.level_first.size() - 2;
   for (int l = 1; l <= nlev; ++l)
     for (int k = pl.level_first[l]; k < pl.level_first[l + 1]; ++k) {
@@ -811,20 +1052,17 @@ hps_status hps_iface_plan_fronts(int p, int nx, int ny, int *nS, int *nE, int *l
   return HPS_OK;
 }
 
-hps_status hps_iface_create(hps_ctx *ctx, int p, int nx, int ny, hps_iface **out) {
+hps_status hps_iface_create_orders(hps_ctx *ctx, int nx, int ny, const int *orders,
+                                   const long long *s_off, const long long *b_off,
+                                   hps_iface **out) {
   if (!ctx || !out) return HPS_ERR_INVALID;
   *out = nullptr;
   hps_iface *it = new (std::nothrow) hps_iface;
   if (!it) return HPS_ERR_OOM;
-  try {
-    const hps_status st = make_plan(p, nx, ny, it->plan);
-    if (st != HPS_OK) {
-      delete it;
-      return st;
-    }
-  } catch (...) {
+  const hps_status st = plan_checked(nx, ny, orders, s_off, b_off, it->plan);
+  if (st != HPS_OK) {
     delete it;
-    return HPS_ERR_OOM;
+    return st;
   }
   it->stream = hps::ctx_stream(ctx);
   const Plan &pl = it->plan;
@@ -833,19 +1071,26 @@ hps_status hps_iface_create(hps_ctx *ctx, int p, int nx, int ny, hps_iface **out
   auto alloc = [&](void **ptr, size_t bytes) {
     if (e == hipSuccess && bytes) e = hipMalloc(ptr, bytes);
   };
+  auto upload = [&](void *dst, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
   alloc((void **)&it->d_front, nf * sizeof(Front));
+  alloc((void **)&it->d_leaf, pl.leaves.size() * sizeof(LeafD));
+  alloc((void **)&it->d_tlist, pl.tlist.size() * sizeof(int));
+  alloc((void **)&it->d_tab, pl.tab.size() * sizeof(double));
   alloc((void **)&it->d_ar, pl.ndouble * sizeof(double));
   alloc((void **)&it->d_ia, pl.ints.size() * sizeof(int));
   alloc((void **)&it->d_info, (nf + 1) * sizeof(int));
-  alloc((void **)&it->d_rl, (size_t)pl.L * pl.nb * sizeof(double));
+  alloc((void **)&it->d_rl, pl.nslot * sizeof(double));
   alloc((void **)&it->d_u, (size_t)pl.nnode * sizeof(double));
-  if (e == hipSuccess && nf)
-    e = hipMemcpy(it->d_front, pl.fronts.data(), nf * sizeof(Front), hipMemcpyHostToDevice);
-  if (e == hipSuccess && !pl.ints.empty())
-    e = hipMemcpy(it->d_ia, pl.ints.data(), pl.ints.size() * sizeof(int),
-                  hipMemcpyHostToDevice);
+  upload(it->d_front, pl.fronts.data(), nf * sizeof(Front));
+  upload(it->d_leaf, pl.leaves.data(), pl.leaves.size() * sizeof(LeafD));
+  upload(it->d_tlist, pl.tlist.data(), pl.tlist.size() * sizeof(int));
+  upload(it->d_tab, pl.tab.data(), pl.tab.size() * sizeof(double));
+  upload(it->d_ia, pl.ints.data(), pl.ints.size() * sizeof(int));
   if (e == hipSuccess) e = allow_lds(k_nd_getrf, getrf_lds(kMaxSep));
   if (e == hipSuccess) e = allow_lds(k_nd_getrs, getrs_lds(kMaxSep));
+  if (e == hipSuccess) e = allow_lds(k_nd_leaf_transform, transform_lds(HPS_P_MAX - 2, 4 * (HPS_P_MAX - 2)));
   if (e != hipSuccess) {
     hps_iface_destroy(it);
     return from_hip(e);
@@ -854,10 +1099,19 @@ hps_status hps_iface_create(hps_ctx *ctx, int p, int nx, int ny, hps_iface **out
   return HPS_OK;
 }
 
+hps_status hps_iface_create(hps_ctx *ctx, int p, int nx, int ny, hps_iface **out) {
+  if (!ctx || !out || nx < 1 || ny < 1) return HPS_ERR_INVALID;
+  const std::vector<int> o = uniform_orders(p, nx, ny);
+  return hps_iface_create_orders(ctx, nx, ny, o.data(), nullptr, nullptr, out);
+}
+
 hps_status hps_iface_factor(hps_iface *it, const double *S, int *info, int flags) {
   if (!it || !S) return HPS_ERR_INVALID;
   const Plan &pl = it->plan;
   const hipStream_t st = it->stream;
+  if (!pl.tlist.empty())
+    k_nd_leaf_transform<<<(int)pl.tlist.size(), 256, transform_lds(pl.t_max_m, pl.t_max_ne),
+                          st>>>(it->d_leaf, it->d_tlist, S, it->d_tab, it->d_ar);
   const int nlev = (int)pl.level_first.size() - 2;
   for (int l = 1; l <= nlev; ++l) {
     const int first = pl.level_first[l], cnt = pl.level_first[l + 1] - first;
@@ -865,7 +1119,7 @@ hps_status hps_iface_factor(hps_iface *it, const double *S, int *info, int flags
     const int ms = pl.level_max_s[l], me = pl.level_max_e[l];
     const long long nn = (long long)(ms + me) * (ms + me);
     const int gx = (int)std::min<long long>((nn + 255) / 256, 4096);
-    k_nd_front<<<dim3(gx, cnt), 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia, S, pl.nb);
+    k_nd_front<<<dim3(gx, cnt), 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia, S);
     k_nd_getrf<<<cnt, kFactorThreads, getrf_lds(ms), st>>>(it->d_front, first, it->d_ar,
                                                             it->d_ia, it->d_info);
     if (me > 0) {
@@ -898,15 +1152,12 @@ hps_status hps_iface_solve(hps_iface *it, const double *S, const double *w, cons
   const Plan &pl = it->plan;
   const hipStream_t st = it->stream;
   const int nlev = (int)pl.level_first.size() - 2;
-  const size_t nslot = (size_t)pl.L * pl.nb;
-  const int gs = (int)((nslot + 255) / 256);
-  k_nd_leaf_rhs<<<gs, 256, 0, st>>>(pl.L, pl.nx, pl.ny, pl.m, S, w, g, it->d_rl);
+  k_nd_leaf_rhs<<<pl.L, 128, 0, st>>>(it->d_leaf, S, w, g, it->d_tab, it->d_rl, it->d_ar);
   for (int l = 1; l <= nlev; ++l) {
     const int first = pl.level_first[l], cnt = pl.level_first[l + 1] - first;
     if (cnt <= 0) continue;
     const int ms = pl.level_max_s[l], me = pl.level_max_e[l];
-    k_nd_front_rhs<<<cnt, 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia, it->d_rl,
-                                        pl.nb);
+    k_nd_front_rhs<<<cnt, 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia, it->d_rl);
     k_nd_getrs<<<dim3(1, cnt), kSolveThreads, getrs_lds(ms), st>>>(it->d_front, first,
                                                                   it->d_ar, it->d_ia, 1);
     if (me > 0)
@@ -919,7 +1170,7 @@ hps_status hps_iface_solve(hps_iface *it, const double *S, const double *w, cons
     k_nd_down<<<dim3((ms + 3) / 4, cnt), 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia,
                                                        it->d_u);
   }
-  k_nd_output<<<gs, 256, 0, st>>>(pl.L, pl.nx, pl.ny, pl.m, it->d_u, g, ub);
+  k_nd_output<<<pl.L, 128, 0, st>>>(it->d_leaf, it->d_u, g, it->d_tab, ub);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && (flags & HPS_SYNC)) e = hipStreamSynchronize(st);
   return from_hip(e);
@@ -934,6 +1185,9 @@ hps_status hps_iface_destroy(hps_iface *it) {
     if (first == hipSuccess) first = e;
   };
   rel(it->d_front);
+  rel(it->d_leaf);
+  rel(it->d_tlist);
+  rel(it->d_tab);
   rel(it->d_ar);
   rel(it->d_ia);
   rel(it->d_info);

@@ -178,14 +178,56 @@ def dirichlet_data(G: GroupView):
     return G.problem.g(xy[..., 0], xy[..., 1], torch).contiguous()
 
 
+def dirichlet_data_batch(batch: "LeafBatch"):
+    """dirichlet_data of every group, concatenated in the batch's slot layout."""
+    torch = _torch()
+    return torch.cat([dirichlet_data(G).reshape(-1) for G in batch.groups]).contiguous()
+
+
+def interface_unknowns(problem) -> int:
+    """Unknowns of the reduced system: the nodes of every edge shared by two
+    leaves, at the lower of the two orders."""
+    nx, ny = problem.nx, problem.ny
+    orders = getattr(problem, "orders", None)
+    if orders is None:
+        return ((nx - 1) * ny + nx * (ny - 1)) * (problem.p - 2)
+    o = np.asarray(orders).reshape(ny, nx) - 2
+    return int(np.minimum(o[:, :-1], o[:, 1:]).sum() + np.minimum(o[:-1, :], o[1:, :]).sum())
+
+
+def batch_offsets(batch: "LeafBatch", problem):
+    """Offsets of every grid leaf's S and boundary slots in a batch whose
+    groups are `problem`'s leaf sets (one per order, in `problem.groups()`
+    order): leaf t's S starts at s_off[t] doubles, its slots at b_off[t]."""
+    s_off = np.zeros(problem.nleaf, dtype=np.int64)
+    b_off = np.zeros(problem.nleaf, dtype=np.int64)
+    s0 = b0 = 0
+    for G in batch.groups:
+        k = np.arange(G.nleaf)
+        s_off[G.problem.leaves] = s0 + k * G.nb * G.nb
+        b_off[G.problem.leaves] = b0 + k * G.nb
+        s0 += G.nleaf * G.nb * G.nb
+        b0 += G.nleaf * G.nb
+    return s_off, b_off
+
+
 class InterfaceSolver:
     """The library's nested-dissection solve of the reduced system for one
-    problem (a rectangle of nx x ny leaves of one order)."""
+    problem: a rectangle of nx x ny leaves of one order, or a MixedProblem
+    (orders per leaf) condensed by `batch` with one group per order."""
 
-    def __init__(self, ctx: int, problem: Problem):
+    def __init__(self, ctx: int, problem, batch: "LeafBatch" = None):
         self.problem = problem
-        self.plan = hps.hps_iface_plan(problem.p, problem.nx, problem.ny)
-        self.it = hps.hps_iface_create(ctx, problem.p, problem.nx, problem.ny)
+        orders = getattr(problem, "orders", None)
+        if orders is None:
+            self.plan = hps.hps_iface_plan(problem.p, problem.nx, problem.ny)
+            self.it = hps.hps_iface_create(ctx, problem.p, problem.nx, problem.ny)
+        else:
+            if batch is None:
+                raise ValueError("a problem with per-leaf orders needs its batch for the layout")
+            s_off, b_off = batch_offsets(batch, problem)
+            self.plan = hps.hps_iface_plan_orders(problem.nx, problem.ny, orders)
+            self.it = hps.hps_iface_create_orders(ctx, problem.nx, problem.ny, orders, s_off, b_off)
 
     def factor(self, S, info=None, sync: bool = False, allow=(hps.HPS_OK,)):
         return hps.hps_iface_factor(self.it, S, info, hps.HPS_SYNC if sync else 0, allow=allow)

@@ -37,7 +37,8 @@ EXPORTED = (
     "hps_leaf_condense", "hps_leaf_recover", "hps_batch_export", "hps_batch_stats",
     "hps_batch_destroy", "hps_ctx_set_timing", "hps_ctx_phase_times", "hps_batch_set_tuning",
     "hps_leaf_condense_noalloc", "hps_batch_redo_flags", "hps_batch_lanes",
-    "hps_iface_plan", "hps_iface_plan_fronts", "hps_iface_create", "hps_iface_factor", "hps_iface_solve",
+    "hps_iface_plan", "hps_iface_plan_fronts", "hps_iface_create", "hps_iface_plan_orders",
+    "hps_iface_create_orders", "hps_iface_factor", "hps_iface_solve",
     "hps_iface_destroy",
 )
 
@@ -131,6 +132,14 @@ def load(path: str = LIB_PATH):
     L.hps_iface_plan_fronts.restype = i
     L.hps_iface_plan_fronts.argtypes = [i, i, i, ctypes.POINTER(ip), ctypes.POINTER(ip),
                                         ctypes.POINTER(ip)]
+    L.hps_iface_plan_orders.restype = i
+    L.hps_iface_plan_orders.argtypes = [i, i, ctypes.POINTER(ip), ctypes.POINTER(ip),
+                                        ctypes.POINTER(ip), ctypes.POINTER(ip),
+                                        ctypes.POINTER(d), ctypes.POINTER(ctypes.c_size_t)]
+    L.hps_iface_create_orders.restype = i
+    L.hps_iface_create_orders.argtypes = [vp, i, i, ctypes.POINTER(ip),
+                                          ctypes.POINTER(ctypes.c_longlong),
+                                          ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(vp)]
     L.hps_iface_create.restype = i
     L.hps_iface_create.argtypes = [vp, i, i, i, ctypes.POINTER(vp)]
     L.hps_iface_factor.restype = i
@@ -314,6 +323,37 @@ def hps_iface_plan_fronts(p: int, nx: int, ny: int):
     a, b, c = (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))(), (ctypes.c_int * max(n, 1))()
     _check(load().hps_iface_plan_fronts(int(p), int(nx), int(ny), a, b, c), "hps_iface_plan_fronts")
     return list(a)[:n], list(b)[:n], list(c)[:n]
+
+
+def _int_array(v):
+    v = [int(x) for x in v]
+    return (ctypes.c_int * max(len(v), 1))(*v)
+
+
+def _ll_array(v):
+    if v is None:
+        return None
+    v = [int(x) for x in v]
+    return (ctypes.c_longlong * max(len(v), 1))(*v)
+
+
+def hps_iface_plan_orders(nx: int, ny: int, orders) -> dict:
+    """Host-only plan for per-leaf orders (leaf t = ix + nx*iy)."""
+    nf, lv, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    fl, by = ctypes.c_double(), ctypes.c_size_t()
+    _check(load().hps_iface_plan_orders(int(nx), int(ny), _int_array(orders), ctypes.byref(nf),
+                                        ctypes.byref(lv), ctypes.byref(ms), ctypes.byref(fl),
+                                        ctypes.byref(by)), "hps_iface_plan_orders")
+    return {"fronts": nf.value, "levels": lv.value, "max_separator": ms.value,
+            "factor_flop": fl.value, "bytes": by.value}
+
+
+def hps_iface_create_orders(ctx: int, nx: int, ny: int, orders, s_off=None, b_off=None) -> int:
+    out = ctypes.c_void_p()
+    _check(load().hps_iface_create_orders(ctypes.c_void_p(ctx), int(nx), int(ny),
+                                          _int_array(orders), _ll_array(s_off), _ll_array(b_off),
+                                          ctypes.byref(out)), "hps_iface_create_orders")
+    return out.value
 
 
 def hps_iface_create(ctx: int, p: int, nx: int, ny: int) -> int:

@@ -268,6 +268,22 @@ class LeafSet:
     def f(self):
         return self.parent.f
 
+    @property
+    def g(self):
+        return self.parent.g
+
+    @property
+    def exact(self):
+        return self.parent.exact
+
+    @property
+    def kappa(self) -> float:
+        return self.parent.kappa
+
+    @property
+    def meta(self) -> dict:
+        return self.parent.meta
+
     def boxes(self) -> np.ndarray:
         return self.parent.boxes()[self.leaves]
 

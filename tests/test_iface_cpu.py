@@ -63,3 +63,40 @@ def test_plan_rejects(lib, p, nx, ny):
     with pytest.raises(hps.HpsError) as e:
         hps.hps_iface_plan(p, nx, ny)
     assert e.value.status == hps.HPS_ERR_INVALID
+
+
+@pytest.mark.parametrize("nx,ny,orders", [(4, 4, (8, 12)), (5, 3, (8, 10, 16)), (32, 32, None)])
+def test_plan_with_orders(lib, nx, ny, orders):
+    """Per-leaf orders: one front per leaf but one, and the root separator
+    carries, on every cut edge, the lower of its two leaves' orders."""
+    import numpy as np
+    from oracle import mixed as mx
+    from paper_2211_14969_amd import inputs
+    if orders is None:
+        prob = inputs.mixed_bump()
+        o = prob.orders
+    else:
+        rng = np.random.default_rng(nx * ny)
+        o = rng.choice(np.asarray(orders), size=nx * ny)
+    plan = hps.hps_iface_plan_orders(nx, ny, o)
+    assert plan["fronts"] == nx * ny - 1
+    num = mx.numbering(nx, ny, o)
+    # the root cut: the longer side is halved first
+    if nx >= ny:
+        mid = nx // 2
+        cut = [mid + (nx + 1) * iy for iy in range(ny)]
+    else:
+        mid = ny // 2
+        cut = [(nx + 1) * ny + ix + nx * mid for ix in range(nx)]
+    root = sum(int(num.m_edge[e]) for e in cut)
+    assert plan["max_separator"] >= root
+    # one order everywhere is the uniform plan exactly
+    u = hps.hps_iface_plan_orders(nx, ny, [int(o[0])] * (nx * ny))
+    assert u == hps.hps_iface_plan(int(o[0]), nx, ny)
+
+
+def test_plan_orders_rejects(lib):
+    with pytest.raises(hps.HpsError):
+        hps.hps_iface_plan_orders(2, 2, [8, 8, 3, 8])
+    with pytest.raises(hps.HpsError):
+        hps.hps_iface_plan_orders(2, 2, [8, 8, 8, 40])
