@@ -50,6 +50,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxSep = HPS_IFACE_MAX_SEPARATOR;
 constexpr int kFactorThreads = 512;   // LU of one separator block per workgroup
 constexpr int kSolveThreads = 512;    // 16 right-hand sides per workgroup
+constexpr int kSplitLU = 256;         // separators from this size: LU in two launches per panel
 
 // One front as the kernels see it.  Offsets are in doubles or ints.  A
 // child's Schur complement and reduced right-hand side live in the FP64
@@ -192,6 +193,121 @@ size_t getrf_lds(int n) {
   return sizeof(double) * ((size_t)n16 * 16 + nw) + sizeof(int) * (nw + 16 + (size_t)n + 1);
 }
 
+// One 16-column panel of the LU of an n x n row-major A, columns c0 ..
+// c0+15: the panel factored in LDS (P, [n16][16]) with the pivot rule of
+// LAPACK getrf (largest magnitude, ties to the lowest row), written back, its
+// row exchanges applied to every other column (and to `perm`, the row order:
+// row i of P A is row perm[i] of A), then U12 = L11^{-1} A12.  A zero (or
+// NaN) pivot sets *zp to its column (1-based) unless already set.  All
+// threads of the workgroup call it; it ends with a barrier.
+template <int NT>
+__device__ void nd_panel(double *A, int n, int c0, double *P, double *redv, int *redi, int *pivl,
+                         int *perm, int *zp) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int w = min(16, n - c0), rows = n - c0;
+  for (int e = tid; e < rows * 16; e += NT) {
+    const int r = e >> 4, c = e & 15;
+    P[e] = c < w ? A[(size_t)(c0 + r) * n + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int lc = 0; lc < w; ++lc) {
+    double bv = -1.0;
+    int br = INT_MAX;
+    for (int r = lc + tid; r < rows; r += NT) {
+      const double a = fabs(P[r * 16 + lc]);
+      if (a > bv) {
+        bv = a;
+        br = r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int orow = __shfl_xor(br, off);
+      if (ov > bv || (ov == bv && orow < br)) {
+        bv = ov;
+        br = orow;
+      }
+    }
+    if (lane == 0) {
+      redv[wv] = bv;
+      redi[wv] = br;
+    }
+    __syncthreads();
+    double pv = redv[0];
+    int pr = redi[0];
+    for (int k = 1; k < NW; ++k) {
+      if (redv[k] > pv || (redv[k] == pv && redi[k] < pr)) {
+        pv = redv[k];
+        pr = redi[k];
+      }
+    }
+    // no candidate (the whole column NaN): keep the row, flag the pivot
+    if (pr >= rows) pr = lc;
+    if (pr != lc && tid < 16) {
+      const double a = P[lc * 16 + tid];
+      P[lc * 16 + tid] = P[pr * 16 + tid];
+      P[pr * 16 + tid] = a;
+    }
+    if (tid == 0) {
+      pivl[lc] = c0 + pr;
+      if (pr != lc) {
+        const int a = perm[c0 + lc];
+        perm[c0 + lc] = perm[c0 + pr];
+        perm[c0 + pr] = a;
+      }
+      if (!(pv > 0.0) && *zp == 0) *zp = c0 + lc + 1;
+    }
+    __syncthreads();
+    const double d = P[lc * 16 + lc];
+    if (d != 0.0) {
+      const double inv = 1.0 / d;
+      for (int r = lc + 1 + tid; r < rows; r += NT) {
+        const double l = P[r * 16 + lc] * inv;
+        P[r * 16 + lc] = l;
+        for (int j = lc + 1; j < w; ++j) P[r * 16 + j] -= l * P[lc * 16 + j];
+      }
+    }
+    __syncthreads();
+  }
+  // panel back, and its row exchanges applied to every other column
+  for (int e = tid; e < rows * 16; e += NT) {
+    const int r = e >> 4, c = e & 15;
+    if (c < w) A[(size_t)(c0 + r) * n + c0 + c] = P[e];
+  }
+  for (int j = tid; j < n; j += NT) {
+    if (j >= c0 && j < c0 + w) continue;
+    for (int lc = 0; lc < w; ++lc) {
+      const int r2 = pivl[lc];
+      if (r2 != c0 + lc) {
+        double *a = A + (size_t)(c0 + lc) * n + j;
+        double *b = A + (size_t)r2 * n + j;
+        const double t = *a;
+        *a = *b;
+        *b = t;
+      }
+    }
+  }
+  __syncthreads();
+  if (c0 + 16 >= n) return;   // last panel: nothing to the right
+  // U12 = L11^{-1} A12 (unit lower L11 from the panel)
+  for (int j = c0 + 16 + tid; j < n; j += NT) {
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = A[(size_t)(c0 + k) * n + j];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+      // one row of L11 at a time (keeps its loads from piling up in registers)
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int i = 0; i < k; ++i) x[k] -= P[k * 16 + i] * x[i];
+    }
+#pragma unroll
+    for (int k = 1; k < 16; ++k) A[(size_t)(c0 + k) * n + j] = x[k];
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kFactorThreads) void k_nd_getrf(const Front *fr, int first,
                                                             double *ar, int *ia, int *info) {
   constexpr int NT = kFactorThreads, NW = NT / 64;
@@ -212,107 +328,8 @@ __global__ __launch_bounds__(kFactorThreads) void k_nd_getrf(const Front *fr, in
   if (tid == 0) *zp = 0;
   __syncthreads();
   for (int c0 = 0; c0 < n; c0 += 16) {
-    const int w = min(16, n - c0), rows = n - c0;
-    for (int e = tid; e < rows * 16; e += NT) {
-      const int r = e >> 4, c = e & 15;
-      P[e] = c < w ? A[(size_t)(c0 + r) * n + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int lc = 0; lc < w; ++lc) {
-      double bv = -1.0;
-      int br = INT_MAX;
-      for (int r = lc + tid; r < rows; r += NT) {
-        const double a = fabs(P[r * 16 + lc]);
-        if (a > bv) {
-          bv = a;
-          br = r;
-        }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int orow = __shfl_xor(br, off);
-        if (ov > bv || (ov == bv && orow < br)) {
-          bv = ov;
-          br = orow;
-        }
-      }
-      if (lane == 0) {
-        redv[wv] = bv;
-        redi[wv] = br;
-      }
-      __syncthreads();
-      double pv = redv[0];
-      int pr = redi[0];
-      for (int k = 1; k < NW; ++k) {
-        if (redv[k] > pv || (redv[k] == pv && redi[k] < pr)) {
-          pv = redv[k];
-          pr = redi[k];
-        }
-      }
-      // no candidate (the whole column NaN): keep the row, flag the pivot
-      if (pr >= rows) pr = lc;
-      if (pr != lc && tid < 16) {
-        const double a = P[lc * 16 + tid];
-        P[lc * 16 + tid] = P[pr * 16 + tid];
-        P[pr * 16 + tid] = a;
-      }
-      if (tid == 0) {
-        pivl[lc] = c0 + pr;
-        if (pr != lc) {
-          const int a = perm[c0 + lc];
-          perm[c0 + lc] = perm[c0 + pr];
-          perm[c0 + pr] = a;
-        }
-        if (!(pv > 0.0) && *zp == 0) *zp = c0 + lc + 1;
-      }
-      __syncthreads();
-      const double d = P[lc * 16 + lc];
-      if (d != 0.0) {
-        const double inv = 1.0 / d;
-        for (int r = lc + 1 + tid; r < rows; r += NT) {
-          const double l = P[r * 16 + lc] * inv;
-          P[r * 16 + lc] = l;
-          for (int j = lc + 1; j < w; ++j) P[r * 16 + j] -= l * P[lc * 16 + j];
-        }
-      }
-      __syncthreads();
-    }
-    // panel back, and its row exchanges applied to every other column
-    for (int e = tid; e < rows * 16; e += NT) {
-      const int r = e >> 4, c = e & 15;
-      if (c < w) A[(size_t)(c0 + r) * n + c0 + c] = P[e];
-    }
-    for (int j = tid; j < n; j += NT) {
-      if (j >= c0 && j < c0 + w) continue;
-      for (int lc = 0; lc < w; ++lc) {
-        const int r2 = pivl[lc];
-        if (r2 != c0 + lc) {
-          double *a = A + (size_t)(c0 + lc) * n + j;
-          double *b = A + (size_t)r2 * n + j;
-          const double t = *a;
-          *a = *b;
-          *b = t;
-        }
-      }
-    }
-    __syncthreads();
-    if (c0 + 16 >= n) break;   // last panel: nothing to the right
-    // U12 = L11^{-1} A12 (unit lower L11 from the panel)
-    for (int j = c0 + 16 + tid; j < n; j += NT) {
-      double x[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = A[(size_t)(c0 + k) * n + j];
-#pragma unroll
-      for (int k = 1; k < 16; ++k) {
-        // one row of L11 at a time (keeps its loads from piling up in registers)
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int i = 0; i < k; ++i) x[k] -= P[k * 16 + i] * x[i];
-      }
-#pragma unroll
-      for (int k = 1; k < 16; ++k) A[(size_t)(c0 + k) * n + j] = x[k];
-    }
-    __syncthreads();
+    nd_panel<NT>(A, n, c0, P, redv, redi, pivl, perm, zp);
+    if (c0 + 16 >= n) break;
     // trailing update A22 -= L21 U12, strips of one row tile x four column tiles
     const int r0 = c0 + 16;
     const int nt = (n - r0 + 15) >> 4, ns = (nt + 3) >> 2;
@@ -356,6 +373,89 @@ __global__ __launch_bounds__(kFactorThreads) void k_nd_getrf(const Front *fr, in
   int *permg = ia + f.perm;
   for (int i = tid; i < n; i += NT) permg[i] = perm[i];
   if (tid == 0) info[fi] = *zp;
+}
+
+// The same LU for the few large fronts at the top of the tree, in two
+// launches per panel: k_nd_panel (one workgroup per front: the panel, its
+// exchanges and U12, with the row order and the zero-pivot flag kept in
+// global memory between launches) and k_nd_trail (the trailing update of
+// every front of the level, one 64 x 64 tile per workgroup).
+__global__ __launch_bounds__(kFactorThreads) void k_nd_panel(const Front *fr, int first,
+                                                            double *ar, int *ia, int *info,
+                                                            int c0) {
+  constexpr int NT = kFactorThreads, NW = NT / 64;
+  extern __shared__ double lds[];
+  const int fi = first + blockIdx.x;
+  const Front f = fr[fi];
+  const int n = f.nS;
+  if (c0 >= n) return;
+  const int n16 = (n + 15) & ~15;
+  double *P = lds;
+  double *redv = P + (size_t)n16 * 16;
+  int *redi = (int *)(redv + NW);
+  int *pivl = redi + NW;
+  int *perm = ia + f.perm;
+  if (c0 == 0) {
+    for (int i = threadIdx.x; i < n; i += NT) perm[i] = i;
+    if (threadIdx.x == 0) info[fi] = 0;
+    __syncthreads();
+  }
+  nd_panel<NT>(ar + f.fss, n, c0, P, redv, redi, pivl, perm, info + fi);
+}
+
+__global__ __launch_bounds__(256) void k_nd_trail(const Front *fr, int first, double *ar,
+                                                  int c0) {
+  const Front f = fr[first + blockIdx.y];
+  const int n = f.nS, r0 = c0 + 16;
+  if (r0 >= n) return;
+  const int tn = (n - r0 + 63) >> 6;
+  if ((int)blockIdx.x >= tn * tn) return;
+  const int bi = blockIdx.x / tn, bj = blockIdx.x - bi * tn;
+  double *A = ar + f.fss;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wr = wv >> 1, wc = wv & 1;
+  const int rb = r0 + 64 * bi + 32 * wr, cb = r0 + 64 * bj + 32 * wc;
+  d4 acc[2][2];
+#pragma unroll
+  for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+    for (int j2 = 0; j2 < 2; ++j2) {
+      const int col = cb + 16 * j2 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rb + 16 * i2 + 4 * q + (lane >> 4);
+        acc[i2][j2][q] = (row < n && col < n) ? A[(size_t)row * n + col] : 0.0;
+      }
+    }
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = c0 + 4 * s + (lane >> 4);
+    double a[2], b[2];
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2) {
+      const int row = rb + 16 * i2 + (lane & 15);
+      a[i2] = row < n ? -A[(size_t)row * n + k] : 0.0;
+    }
+#pragma unroll
+    for (int j2 = 0; j2 < 2; ++j2) {
+      const int col = cb + 16 * j2 + (lane & 15);
+      b[j2] = col < n ? A[(size_t)k * n + col] : 0.0;
+    }
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+      for (int j2 = 0; j2 < 2; ++j2) acc[i2][j2] = mma(a[i2], b[j2], acc[i2][j2]);
+  }
+#pragma unroll
+  for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+    for (int j2 = 0; j2 < 2; ++j2) {
+      const int col = cb + 16 * j2 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rb + 16 * i2 + 4 * q + (lane >> 4);
+        if (row < n && col < n) A[(size_t)row * n + col] = acc[i2][j2][q];
+      }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1089,6 +1189,7 @@ hps_status hps_iface_create_orders(hps_ctx *ctx, int nx, int ny, const int *orde
   upload(it->d_tab, pl.tab.data(), pl.tab.size() * sizeof(double));
   upload(it->d_ia, pl.ints.data(), pl.ints.size() * sizeof(int));
   if (e == hipSuccess) e = allow_lds(k_nd_getrf, getrf_lds(kMaxSep));
+  if (e == hipSuccess) e = allow_lds(k_nd_panel, getrf_lds(kMaxSep));
   if (e == hipSuccess) e = allow_lds(k_nd_getrs, getrs_lds(kMaxSep));
   if (e == hipSuccess) e = allow_lds(k_nd_leaf_transform, transform_lds(HPS_P_MAX - 2, 4 * (HPS_P_MAX - 2)));
   if (e != hipSuccess) {
@@ -1120,8 +1221,20 @@ hps_status hps_iface_factor(hps_iface *it, const double *S, int *info, int flags
     const long long nn = (long long)(ms + me) * (ms + me);
     const int gx = (int)std::min<long long>((nn + 255) / 256, 4096);
     k_nd_front<<<dim3(gx, cnt), 256, 0, st>>>(it->d_front, first, it->d_ar, it->d_ia, S);
-    k_nd_getrf<<<cnt, kFactorThreads, getrf_lds(ms), st>>>(it->d_front, first, it->d_ar,
-                                                            it->d_ia, it->d_info);
+    if (ms >= kSplitLU) {
+      // few large fronts: the trailing updates spread over the whole GPU
+      for (int c0 = 0; c0 < ms; c0 += 16) {
+        k_nd_panel<<<cnt, kFactorThreads, getrf_lds(ms), st>>>(it->d_front, first, it->d_ar,
+                                                                it->d_ia, it->d_info, c0);
+        if (c0 + 16 < ms) {
+          const int tn = (ms - c0 - 16 + 63) / 64;
+          k_nd_trail<<<dim3(tn * tn, cnt), 256, 0, st>>>(it->d_front, first, it->d_ar, c0);
+        }
+      }
+    } else {
+      k_nd_getrf<<<cnt, kFactorThreads, getrf_lds(ms), st>>>(it->d_front, first, it->d_ar,
+                                                              it->d_ia, it->d_info);
+    }
     if (me > 0) {
       k_nd_getrs<<<dim3((me + 15) / 16, cnt), kSolveThreads, getrs_lds(ms), st>>>(
           it->d_front, first, it->d_ar, it->d_ia, 0);
