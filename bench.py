@@ -38,10 +38,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 # Calibrated HBM traffic of one factorisation launch, from rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE (KiB per dispatch, FETCH scaled by 2.0 and WRITE by
-# 1.0 against a 1 GiB device copy), keyed by the sha256 prefix of the kernel
-# source it was measured on, the workload and the precision.
+# 1.0 against a 1 GiB device copy), keyed by the hash of the kernel source it
+# was measured on (kernel_source_hash), the workload and the precision.
 MEASURED_TRAFFIC = {
-    ("6c44858364734b8a", "bumps_32x32_p32", "fp64"): {
+    ("1024084fa514763c", "bumps_32x32_p32", "fp64"): {
         "kernel": "k_factor_ll<double, 8, 8, 2, 1>",
         "fetch_bytes": 39208856.510 * 2.0 * 1024, "write_bytes": 8290014.812 * 1.0 * 1024},
 }
@@ -59,16 +59,20 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash() -> str:
-    """sha256 prefix of the kernel source with comments and whitespace
-    removed: edits of comments keep a traffic measurement valid, any change
-    of code invalidates it."""
+def kernel_source_hash(kernel: str = "k_factor_ll") -> str:
+    """sha256 prefix of the kernel file up to the end of `kernel`'s
+    definition (its helpers come before it; the solves and launchers after
+    it do not change its traffic), with comments and whitespace removed:
+    edits of comments keep a traffic measurement valid, any change of that
+    code invalidates it."""
     import hashlib
     import re
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "paper_2211_14969_amd", "csrc", "hps_kernels.hip")
     with open(path) as fh:
         src = fh.read()
+    head = src.index(kernel + "(Geom g")
+    src = src[:src.index("\n}\n", head) + 3]
     src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
     src = re.sub(r"//[^\n]*", " ", src)
     src = re.sub(r"\s+", " ", src).strip()

@@ -3502,11 +3502,11 @@ hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const 
     if (fp32) return launch_solve_rr<float>(g, nleaf, (const float *)M, piv, o, s, sel);
     return launch_solve_rr<double>(g, nleaf, (const double *)M, piv, o, s, sel);
   }
-  if (fp32) return launch_trisolve<float, 1>(g, nleaf, (float *)M, piv, rstep, o, s, sel);
-  // two column chunks per leaf for the largest FP64 work matrices: twice the
-  // reads of U, but twice the workgroups, each with half the LDS (measured
-  // 7.17 against 8.55 ms at 912 rows; 2.10 against 1.78 ms at 336 rows)
+  // two column chunks per leaf for the largest work matrices: twice the
+  // reads of U, but twice the workgroups, each with half the LDS (FP64:
+  // measured 7.17 against 8.55 ms at 912 rows; 2.10 against 1.78 ms at 336 rows)
   const int nch = (g.R > 512 && g.CT - g.RT >= 2) ? 2 : 1;
+  if (fp32) return launch_trisolve<float, 1>(g, nleaf, (float *)M, piv, rstep, o, s, sel, nch);
   return launch_trisolve<double, 1>(g, nleaf, (double *)M, piv, rstep, o, s, sel, nch);
 }
 
@@ -3548,7 +3548,8 @@ hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv
 // most four).  The register-resident solves already spread a leaf's column
 // tiles over the wavefronts of its one workgroup.
 int refine_chunks(const Geom &g, int it) {
-  if (it <= 1 || solve_rr_applies(g)) return 1;
+  if (solve_rr_applies(g)) return 1;
+  if (it <= 1) return (g.R > 512 && g.CT - g.RT >= 2) ? 2 : 1;   // as the back substitution
   const int tiles = (g.CT * 16 - g.R) / 16;
   const int per = (tiles + kMaxChunks - 1) / kMaxChunks;   // tiles per chunk
   return (tiles + per - 1) / per;
