@@ -2374,6 +2374,221 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Back substitution of the large FP64 work matrices with the right-hand
+// sides in registers (the mirror of the left-looking factorisation's update
+// loop).  k_inv_udiag first inverts every 16 x 16 diagonal block of U (the
+// pivot rows of panel b, columns 16b ...) into the leaf slot's per-panel
+// tiles, which the factorisation no longer needs.  k_backsolve_big then
+// takes 32 right-hand-side columns per workgroup: row tile t of Y sits in
+// the accumulators of wavefront t % NW; for k = RT-1 down to 0 the owner of
+// tile k forms X_k = U_kk^{-1} Y_k and publishes it in LDS, and every tile
+// t < k takes Y_t -= U_tk X_k, with U_tk (the pivot rows of tile t, panel
+// k's columns) streamed into the wavefront's LDS slot a step ahead.  X is
+// written out through LDS, one column of Xt (or u_i) per contiguous row.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_inv_udiag(Geom g, T *M, const int *piv) {
+  __shared__ T Dl[16][16 * 17];
+  __shared__ int pv[16 * 16];
+  const int wi = blockIdx.x, tid = threadIdx.x;
+  const int RT = g.RT, CT = g.CT, R = g.R;
+  T *Ml = M + leaf_stride(g) * wi;
+  T *Lg = Ml + work_elems(g);
+  const int b0 = blockIdx.y * 16;   // 16 diagonal blocks per workgroup
+  const int nbk = min(16, RT - b0);
+  if (nbk <= 0) return;
+  for (int e = tid; e < nbk * 16; e += 256)
+    pv[e] = min(max(piv[(size_t)wi * R + 16 * b0 + e], 0), R - 1);
+  __syncthreads();
+  for (int e = tid; e < nbk * 256; e += 256) {
+    const int bb = e >> 8, s = (e >> 4) & 15, q = e & 15;
+    Dl[bb][s * 17 + q] = Ml[tix<T>(pv[bb * 16 + s], 16 * (b0 + bb) + q, CT)];
+  }
+  __syncthreads();
+  // column j of block bb per thread: U^{-1} e_j by back substitution
+  const int bb = tid >> 4, j = tid & 15;
+  if (bb < nbk) {
+    const T *D = Dl[bb];
+    double z[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int q = i + 1; q < 16; ++q) acc -= (double)D[i * 17 + q] * z[q];
+      z[i] = (i <= j) ? acc / (double)D[i * 17 + i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Lg[(size_t)(b0 + bb) * 256 + i * 16 + j] = (T)z[i];
+  }
+}
+
+template <int NW, int RTW>
+constexpr size_t backsolve_big_lds(int R) {
+  return sizeof(double) * ((size_t)NW * RTW * 256 + 2 * 16 * 32) + sizeof(int) * (size_t)R;
+}
+
+template <int NW, int RTW>
+__global__ void __launch_bounds__(64 * NW, 1) k_backsolve_big(Geom g, const double *M,
+                                                             const int *piv, BackOut o,
+                                                             Sel sel) {
+  using T = double;
+  constexpr int NT = 64 * NW, KT = 2, KW = 16 * KT;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
+  const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
+  const int c0 = blockIdx.y * KT;              // first right-hand-side column tile
+  const int ncol = min(KT, NCT - c0);
+  if (ncol <= 0) return;
+  T *Abuf = (T *)smem;                         // [NW][RTW][256] streamed U tiles
+  T *Xp = Abuf + (size_t)NW * RTW * 256;       // [2][16][KW] published X_k
+  int *pva = (int *)(Xp + 2 * 16 * KW);        // [R] pivot row of each step
+  const T *Ml = M + leaf_stride(g) * wi;
+  const T *Lg = Ml + work_elems(g);            // U_kk^{-1}, row-major per tile
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int r = tid; r < R; r += NT) pva[r] = min(max(piv[(size_t)wi * R + r], 0), R - 1);
+  __syncthreads();
+
+  using Acc = d4;
+  Acc acc[RTW][KT];
+#pragma unroll
+  for (int i = 0; i < RTW; ++i) {
+    const int t = wv + NW * i;
+#pragma unroll
+    for (int c = 0; c < KT; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[i][c][q] = (t < RT && c < ncol)
+                           ? Ml[tix<T>(pva[16 * t + 4 * q + lr], R + 16 * (c0 + c) + lc, CT)]
+                           : 0.0;
+  }
+  // U_tk for tile i into this wavefront's slot i (the tile in row-major order)
+  auto dma_u = [&](int i, int k) {
+    const int t = wv + NW * i;
+    T *dst = Abuf + (size_t)(wv * RTW + i) * 256;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = h * 128 + lane * 2;
+      const T *src = Ml + tix<T>(pva[16 * t + (e >> 4)], 16 * k + (e & 15), CT);
+      __builtin_amdgcn_global_load_lds((const void *)src,
+                                       (__attribute__((address_space(3))) void *)(dst + h * 128),
+                                       16, 0, 0);
+    }
+  };
+  // tile i takes step k's update (operands paired over index 4 lr + kc, as
+  // in the factorisation), its slot refilled at once for step kn
+  auto mma = [&](int i, const T (&b)[KT][4], int kn) {
+    const T *src = Abuf + (size_t)(wv * RTW + i) * 256 + lc * 16 + 4 * lr;
+    T a[4];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) a[kc] = -src[kc];
+    if (kn >= 0 && wv + NW * i < kn) {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the slot has been read
+      dma_u(i, kn);
+    }
+#pragma unroll
+    for (int c = 0; c < KT; ++c) {
+      if (c < ncol) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) acc[i][c] = mfma64(a[kc], b[c][kc], acc[i][c]);
+      }
+    }
+  };
+  // the owner of tile k forms X_k = U_kk^{-1} Y_k (the accumulators are the
+  // B operand: register kc holds row 4 kc + lr) and publishes it
+  auto form = [&](int k, const T (&ui)[4]) {
+    T *xk = Xp + (k & 1) * 16 * KW;
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      if (wv + NW * i != k) continue;
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+        if (c >= ncol) continue;
+        Acc z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) z = mfma64(ui[kc], acc[i][c][kc], z);
+        acc[i][c] = z;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xk[(4 * q + lr) * KW + 16 * c + lc] = z[q];
+      }
+    }
+  };
+  T upre[4];
+  auto load_uinv = [&](int k) {
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) upre[kc] = Lg[(size_t)k * 256 + lc * 16 + 4 * kc + lr];
+  };
+  // X_{RT-1} needs no update; the tiles below it start their loads
+#pragma unroll
+  for (int i = 0; i < RTW; ++i) {
+    const int t = wv + NW * i;
+    if (t < RT - 1) dma_u(i, RT - 1);
+  }
+  if (wv == (RT - 1) % NW) {
+    load_uinv(RT - 1);
+    form(RT - 1, upre);
+  }
+  if (RT >= 2 && wv == (RT - 2) % NW) load_uinv(RT - 2);
+  for (int k = RT - 1; k >= 1; --k) {
+    lds_barrier();
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's loads of step k
+    const T *X = Xp + (k & 1) * 16 * KW;
+    T b[KT][4];
+#pragma unroll
+    for (int c = 0; c < KT; ++c) {
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? X[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
+    }
+    const int kn = k - 1;                      // the next step's panel
+    const int kload = kn >= 1 ? kn : -1;        // tiles t < kn load U_t,kn
+    const bool ahead = wv == kn % NW;          // owner of tile k-1 forms X_{k-1}
+    if (ahead) {
+#pragma unroll
+      for (int i = 0; i < RTW; ++i)
+        if (wv + NW * i == kn) mma(i, b, kload);
+      form(kn, upre);
+    }
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      const int t = wv + NW * i;
+      if (t < k && !(ahead && t == kn)) mma(i, b, kload);
+    }
+    if (kn >= 1 && wv == (kn - 1) % NW) load_uinv(kn - 1);
+  }
+  __syncthreads();
+  // X out through LDS: one column tile at a time, rows contiguous
+  T *Xs = Abuf;                                // [R][17]
+#pragma unroll
+  for (int c = 0; c < KT; ++c) {
+    if (c >= ncol) continue;
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      const int t = wv + NW * i;
+      if (t < RT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[(16 * t + 4 * q + lr) * 17 + lc] = acc[i][c][q];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * ni; e += NT) {
+      const int cc = e / ni, r = e - cc * ni;
+      const int col = 16 * (c0 + c) + cc;
+      if (col >= g.nrhs) continue;
+      const double v = Xs[r * 17 + cc];
+      if (o.mode == BACK_UI) {
+        o.ui[(size_t)leaf * ni + r] = v;
+      } else if (col < nb) {
+        o.Xt[((size_t)leaf * nb + col) * ni + r] = v;
+      } else {
+        o.h[(size_t)leaf * ni + r] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // The refinement correction (forward then backward, FP32 factors) with each
 // wavefront owning one right-hand-side column tile instead: it keeps all RT
 // row tiles of that column tile in its accumulators and walks both
@@ -3496,8 +3711,41 @@ hipError_t launch_solve_rr(const Geom &g, int nleaf, const T *M, const int *piv,
   return launch_solve_rr_t<T, 16, 5, NW, MW>(g, nleaf, M, piv, o, s, sel);
 }
 
+// HPS_BACKSOLVE_BIG=0 turns the register-resident solve of the large FP64
+// work matrices off (the streaming solve then serves them).
+bool backsolve_big_enabled() {
+  static const bool on = [] {
+    const char *v = std::getenv("HPS_BACKSOLVE_BIG");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
+bool backsolve_big_applies(const Geom &g, bool fp32, int mode) {
+  return !fp32 && g.R > 512 && g.RT <= 8 * 8 && (size_t)g.R * 17 <= 8 * 8 * 256 &&
+         (mode == BACK_STORE || mode == BACK_UI) && backsolve_big_enabled();
+}
+
+hipError_t launch_backsolve_big(const Geom &g, int nleaf, double *M, const int *piv,
+                                const BackOut &o, hipStream_t s, const Sel &sel) {
+  hipLaunchKernelGGL(k_inv_udiag<double>, dim3(nleaf, (g.RT + 15) / 16), dim3(256), 0, s, g, M,
+                     piv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = backsolve_big_lds<8, 8>(g.R);
+  if (lds > kLdsLimit) return hipErrorInvalidValue;
+  e = set_lds(k_backsolve_big<8, 8>, lds);
+  if (e != hipSuccess) return e;
+  const int nck = (g.CT - g.RT + 1) / 2;
+  hipLaunchKernelGGL((k_backsolve_big<8, 8>), dim3(nleaf, nck), dim3(512), lds, s, g,
+                     (const double *)M, piv, o, sel);
+  return hipGetLastError();
+}
+
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
+  if (backsolve_big_applies(g, fp32, o.mode))
+    return launch_backsolve_big(g, nleaf, (double *)M, piv, o, s, sel);
   if (solve_rr_applies(g)) {
     if (fp32) return launch_solve_rr<float>(g, nleaf, (const float *)M, piv, o, s, sel);
     return launch_solve_rr<double>(g, nleaf, (const double *)M, piv, o, s, sel);
