@@ -330,7 +330,7 @@ hps_status condense_group(hps_batch *b, const Group &G, const Scratch &sc, hipSt
         HPS_TRY(timed(b->ctx, s, 3, [&] {
           return hps::launch_refine_solve(g, n, sc.ws, sc.piv, sc.rstep, o, nch, s);
         }));
-        nsol = nch;
+        nsol = hps::refine_solve_chunks(g, nch);
       }
       // Leaves the refinement could not bring to tol (A_ii too ill-conditioned
       // for an FP32 factorisation, e.g. near a leaf resonance) are condensed

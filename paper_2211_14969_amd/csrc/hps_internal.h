@@ -100,6 +100,9 @@ hipError_t launch_convcheck(int nleaf, double *norms, double tol, int *conv, int
 // correction solve; more than one only for iterations after the first,
 // where the few leaves left would otherwise leave the GPU idle
 int refine_chunks(const Geom &g, int it);
+// norm slots the correction solve of that many chunks writes (the
+// register-resident solves split by their own column chunks)
+int refine_solve_chunks(const Geom &g, int nch);
 hipError_t launch_collect(int nleaf, int *info, int *list, int *count, int *total, int *redo,
                           hipStream_t s);
 hipError_t launch_schur(const Geom &g, int nleaf, const double *Xt, const double *h,

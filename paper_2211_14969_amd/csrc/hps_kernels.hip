@@ -2375,23 +2375,30 @@ __global__ void __launch_bounds__(64 * NW, MINW) k_solve_rr(Geom g, const T *M, 
 }
 
 // ---------------------------------------------------------------------------
-// Back substitution of the large FP64 work matrices with the right-hand
-// sides in registers (the mirror of the left-looking factorisation's update
-// loop).  k_inv_udiag first inverts every 16 x 16 diagonal block of U (the
-// pivot rows of panel b, columns 16b ...) into the leaf slot's per-panel
-// tiles, which the factorisation no longer needs.  k_backsolve_big then
-// takes 32 right-hand-side columns per workgroup: row tile t of Y sits in
-// the accumulators of wavefront t % NW; for k = RT-1 down to 0 the owner of
-// tile k forms X_k = U_kk^{-1} Y_k and publishes it in LDS, and every tile
-// t < k takes Y_t -= U_tk X_k, with U_tk (the pivot rows of tile t, panel
-// k's columns) streamed into the wavefront's LDS slot a step ahead.  X is
-// written out through LDS, one column of Xt (or u_i) per contiguous row.
+// Triangular solves of the large work matrices with the right-hand sides in
+// registers (the mirror of the left-looking factorisation's update loop).
+// k_inv_udiag first inverts every 16 x 16 diagonal block of the factors
+// (the pivot rows of panel b in columns 16b ...) into the leaf slot's
+// per-panel tile, which the factorisation no longer needs: U_bb^{-1} on and
+// above the diagonal and, for a forward pass, the unit-lower L_bb^{-1}
+// strictly below it.  k_solve_big then takes 32 right-hand-side columns per
+// workgroup: row tile t of the right-hand sides (in pivot order) sits in the
+// FP64 accumulators of wavefront t % NW for the whole solve.  Forward, for
+// k = 0, 1, ...: the owner of tile k forms Y_k = L_kk^{-1} Y_k and publishes
+// it in LDS, and every tile t > k takes Y_t -= L_tk Y_k; backward, for
+// k = RT-1 down to 0: X_k = U_kk^{-1} Y_k, and every tile t < k takes
+// Y_t -= U_tk X_k.  The factor tiles L_tk / U_tk (the pivot rows of tile t,
+// panel k's columns) are streamed into the wavefront's LDS slot by
+// global_load_lds a step ahead; one LDS-only barrier per step.  The result
+// leaves through LDS, every column of Xt (or u_i) as one contiguous row.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_inv_udiag(Geom g, T *M, const int *piv) {
+template <typename T, int PASSES>
+__global__ void __launch_bounds__(256) k_inv_udiag(Geom g, T *M, const int *piv, Sel sel) {
   __shared__ T Dl[16][16 * 17];
   __shared__ int pv[16 * 16];
   const int wi = blockIdx.x, tid = threadIdx.x;
+  int leaf;
+  if (!resolve_leaf(sel, leaf)) return;
   const int RT = g.RT, CT = g.CT, R = g.R;
   T *Ml = M + leaf_stride(g) * wi;
   T *Lg = Ml + work_elems(g);
@@ -2406,53 +2413,71 @@ __global__ void __launch_bounds__(256) k_inv_udiag(Geom g, T *M, const int *piv)
     Dl[bb][s * 17 + q] = Ml[tix<T>(pv[bb * 16 + s], 16 * (b0 + bb) + q, CT)];
   }
   __syncthreads();
-  // column j of block bb per thread: U^{-1} e_j by back substitution
+  // column j of block bb per thread
   const int bb = tid >> 4, j = tid & 15;
   if (bb < nbk) {
     const T *D = Dl[bb];
-    double z[16];
+    double zu[16], zl[16];
 #pragma unroll
     for (int i = 15; i >= 0; --i) {
       double acc = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-      for (int q = i + 1; q < 16; ++q) acc -= (double)D[i * 17 + q] * z[q];
-      z[i] = (i <= j) ? acc / (double)D[i * 17 + i] : 0.0;
+      for (int q = i + 1; q < 16; ++q) acc -= (double)D[i * 17 + q] * zu[q];
+      zu[i] = (i <= j) ? acc / (double)D[i * 17 + i] : 0.0;
+    }
+    if (PASSES & 2) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) acc -= (double)D[i * 17 + q] * zl[q];
+        zl[i] = acc;
+      }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) Lg[(size_t)(b0 + bb) * 256 + i * 16 + j] = (T)z[i];
+    for (int i = 0; i < 16; ++i) {
+      const double v = (i <= j) ? zu[i] : ((PASSES & 2) ? zl[i] : 0.0);
+      Lg[(size_t)(b0 + bb) * 256 + i * 16 + j] = (T)v;
+    }
   }
 }
 
-template <int NW, int RTW>
-constexpr size_t backsolve_big_lds(int R) {
-  return sizeof(double) * ((size_t)NW * RTW * 256 + 2 * 16 * 32) + sizeof(int) * (size_t)R;
+template <typename T, int NW, int RTW>
+constexpr size_t solve_big_lds(int R) {
+  // the streamed tiles' slots, doubling as the [R][17] FP64 staging of the result
+  const size_t slots = sizeof(T) * (size_t)NW * RTW * 256;
+  const size_t stage = sizeof(double) * (size_t)R * 17;
+  return (slots > stage ? slots : stage) + sizeof(double) * 2 * 16 * 32 + sizeof(int) * (size_t)R;
 }
 
-template <int NW, int RTW>
-__global__ void __launch_bounds__(64 * NW, 1) k_backsolve_big(Geom g, const double *M,
-                                                             const int *piv, BackOut o,
-                                                             Sel sel) {
-  using T = double;
+template <typename T, int NW, int RTW, int PASSES>
+__global__ void __launch_bounds__(64 * NW, 1) k_solve_big(Geom g, const T *M, const int *piv,
+                                                         BackOut o, Sel sel) {
   constexpr int NT = 64 * NW, KT = 2, KW = 16 * KT;
+  constexpr int kPer = 1024 / (int)sizeof(T);   // elements per gather instruction
+  constexpr int kIns = 256 / kPer;               // instructions per tile
   extern __shared__ __align__(16) unsigned char smem[];
   const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int leaf;
   if (!resolve_leaf(sel, leaf)) return;
+  if (o.skip && o.skip[leaf]) return;
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
   const int c0 = blockIdx.y * KT;              // first right-hand-side column tile
   const int ncol = min(KT, NCT - c0);
   if (ncol <= 0) return;
-  T *Abuf = (T *)smem;                         // [NW][RTW][256] streamed U tiles
-  T *Xp = Abuf + (size_t)NW * RTW * 256;       // [2][16][KW] published X_k
+  const size_t slot_bytes = sizeof(T) * (size_t)NW * RTW * 256;
+  const size_t stage_bytes = sizeof(double) * (size_t)R * 17;
+  T *Abuf = (T *)smem;                         // [NW][RTW][256] streamed factor tiles
+  double *Xs = (double *)smem;                 // [R][17] result staging (after the passes)
+  double *Xp = (double *)(smem + (slot_bytes > stage_bytes ? slot_bytes : stage_bytes));
   int *pva = (int *)(Xp + 2 * 16 * KW);        // [R] pivot row of each step
   const T *Ml = M + leaf_stride(g) * wi;
-  const T *Lg = Ml + work_elems(g);            // U_kk^{-1}, row-major per tile
+  const T *Lg = Ml + work_elems(g);            // diagonal-block inverses, row-major per tile
   const int lr = lane >> 4, lc = lane & 15;
   for (int r = tid; r < R; r += NT) pva[r] = min(max(piv[(size_t)wi * R + r], 0), R - 1);
   __syncthreads();
 
-  using Acc = d4;
-  Acc acc[RTW][KT];
+  d4 acc[RTW][KT];
 #pragma unroll
   for (int i = 0; i < RTW; ++i) {
     const int t = wv + NW * i;
@@ -2461,32 +2486,34 @@ __global__ void __launch_bounds__(64 * NW, 1) k_backsolve_big(Geom g, const doub
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         acc[i][c][q] = (t < RT && c < ncol)
-                           ? Ml[tix<T>(pva[16 * t + 4 * q + lr], R + 16 * (c0 + c) + lc, CT)]
+                           ? (double)Ml[tix<T>(pva[16 * t + 4 * q + lr], R + 16 * (c0 + c) + lc, CT)]
                            : 0.0;
   }
-  // U_tk for tile i into this wavefront's slot i (the tile in row-major order)
-  auto dma_u = [&](int i, int k) {
+  // factor tile (rows of tile i, panel k's columns) into this wavefront's slot i
+  auto gather = [&](int i, int k) {
     const int t = wv + NW * i;
     T *dst = Abuf + (size_t)(wv * RTW + i) * 256;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int e = h * 128 + lane * 2;
+    for (int h = 0; h < kIns; ++h) {
+      const int e = h * kPer + lane * (16 / (int)sizeof(T));
       const T *src = Ml + tix<T>(pva[16 * t + (e >> 4)], 16 * k + (e & 15), CT);
       __builtin_amdgcn_global_load_lds((const void *)src,
-                                       (__attribute__((address_space(3))) void *)(dst + h * 128),
+                                       (__attribute__((address_space(3))) void *)(dst + h * kPer),
                                        16, 0, 0);
     }
   };
-  // tile i takes step k's update (operands paired over index 4 lr + kc, as
-  // in the factorisation), its slot refilled at once for step kn
-  auto mma = [&](int i, const T (&b)[KT][4], int kn) {
+  // tile i takes the step's update (operands paired over index 4 lr + kc,
+  // as in the factorisation), its slot refilled at once for step kn when
+  // the tile takes that step too
+  auto mma = [&](int i, const double (&b)[KT][4], int kn, bool fwd) {
     const T *src = Abuf + (size_t)(wv * RTW + i) * 256 + lc * 16 + 4 * lr;
-    T a[4];
+    double a[4];
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) a[kc] = -src[kc];
-    if (kn >= 0 && wv + NW * i < kn) {
+    for (int kc = 0; kc < 4; ++kc) a[kc] = -(double)src[kc];
+    const int t = wv + NW * i;
+    if (kn >= 0 && (fwd ? t > kn : t < kn)) {
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the slot has been read
-      dma_u(i, kn);
+      gather(i, kn);
     }
 #pragma unroll
     for (int c = 0; c < KT; ++c) {
@@ -2496,70 +2523,86 @@ __global__ void __launch_bounds__(64 * NW, 1) k_backsolve_big(Geom g, const doub
       }
     }
   };
-  // the owner of tile k forms X_k = U_kk^{-1} Y_k (the accumulators are the
-  // B operand: register kc holds row 4 kc + lr) and publishes it
-  auto form = [&](int k, const T (&ui)[4]) {
-    T *xk = Xp + (k & 1) * 16 * KW;
+  // the owner of tile k applies the diagonal block's inverse (the
+  // accumulators are the B operand: register kc holds row 4 kc + lr) and
+  // publishes the result
+  auto form = [&](int k, const double (&di)[4]) {
+    double *xk = Xp + (k & 1) * 16 * KW;
 #pragma unroll
     for (int i = 0; i < RTW; ++i) {
       if (wv + NW * i != k) continue;
 #pragma unroll
       for (int c = 0; c < KT; ++c) {
         if (c >= ncol) continue;
-        Acc z = {0.0, 0.0, 0.0, 0.0};
+        d4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) z = mfma64(ui[kc], acc[i][c][kc], z);
+        for (int kc = 0; kc < 4; ++kc) z = mfma64(di[kc], acc[i][c][kc], z);
         acc[i][c] = z;
 #pragma unroll
         for (int q = 0; q < 4; ++q) xk[(4 * q + lr) * KW + 16 * c + lc] = z[q];
       }
     }
   };
-  T upre[4];
-  auto load_uinv = [&](int k) {
+  // row lc of the inverse of block k as this lane's A operand: U^{-1} on and
+  // above the diagonal (backward) or unit-lower L^{-1} (forward)
+  double dpre[4];
+  auto load_inv = [&](int k, bool fwd) {
 #pragma unroll
-    for (int kc = 0; kc < 4; ++kc) upre[kc] = Lg[(size_t)k * 256 + lc * 16 + 4 * kc + lr];
+    for (int kc = 0; kc < 4; ++kc) {
+      const int cc = 4 * kc + lr;
+      const double v = (double)Lg[(size_t)k * 256 + lc * 16 + cc];
+      dpre[kc] = fwd ? (lc > cc ? v : (lc == cc ? 1.0 : 0.0)) : (lc <= cc ? v : 0.0);
+    }
   };
-  // X_{RT-1} needs no update; the tiles below it start their loads
-#pragma unroll
-  for (int i = 0; i < RTW; ++i) {
-    const int t = wv + NW * i;
-    if (t < RT - 1) dma_u(i, RT - 1);
-  }
-  if (wv == (RT - 1) % NW) {
-    load_uinv(RT - 1);
-    form(RT - 1, upre);
-  }
-  if (RT >= 2 && wv == (RT - 2) % NW) load_uinv(RT - 2);
-  for (int k = RT - 1; k >= 1; --k) {
-    lds_barrier();
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's loads of step k
-    const T *X = Xp + (k & 1) * 16 * KW;
-    T b[KT][4];
-#pragma unroll
-    for (int c = 0; c < KT; ++c) {
-#pragma unroll
-      for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? X[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
-    }
-    const int kn = k - 1;                      // the next step's panel
-    const int kload = kn >= 1 ? kn : -1;        // tiles t < kn load U_t,kn
-    const bool ahead = wv == kn % NW;          // owner of tile k-1 forms X_{k-1}
-    if (ahead) {
-#pragma unroll
-      for (int i = 0; i < RTW; ++i)
-        if (wv + NW * i == kn) mma(i, b, kload);
-      form(kn, upre);
-    }
+  // one pass: k runs from k_first to k_last (step dir); tiles "after" k in
+  // the pass order take each X_k
+  auto pass = [&](bool fwd) {
+    const int dir = fwd ? 1 : -1;
+    const int kf = fwd ? 0 : RT - 1, kl = fwd ? RT - 1 : 0;
 #pragma unroll
     for (int i = 0; i < RTW; ++i) {
       const int t = wv + NW * i;
-      if (t < k && !(ahead && t == kn)) mma(i, b, kload);
+      if (t < RT && (fwd ? t > kf : t < kf)) gather(i, kf);
     }
-    if (kn >= 1 && wv == (kn - 1) % NW) load_uinv(kn - 1);
-  }
-  __syncthreads();
-  // X out through LDS: one column tile at a time, rows contiguous
-  T *Xs = Abuf;                                // [R][17]
+    if (wv == kf % NW) {
+      load_inv(kf, fwd);
+      form(kf, dpre);
+    }
+    if (RT >= 2 && wv == (kf + dir) % NW) load_inv(kf + dir, fwd);
+    for (int k = kf; k != kl; k += dir) {
+      lds_barrier();
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wavefront's loads of step k
+      const double *X = Xp + (k & 1) * 16 * KW;
+      double b[KT][4];
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          b[c][kc] = c < ncol ? X[(4 * lr + kc) * KW + 16 * c + lc] : 0.0;
+      }
+      const int kn = k + dir;                  // the next step
+      const int kload = kn != kl ? kn : -1;    // tiles after kn gather for it
+      const bool ahead = wv == kn % NW;        // owner of tile kn forms it
+      if (ahead) {
+#pragma unroll
+        for (int i = 0; i < RTW; ++i)
+          if (wv + NW * i == kn) mma(i, b, kload, fwd);
+        form(kn, dpre);
+      }
+#pragma unroll
+      for (int i = 0; i < RTW; ++i) {
+        const int t = wv + NW * i;
+        if (t < RT && (fwd ? t > k : t < k) && !(ahead && t == kn)) mma(i, b, kload, fwd);
+      }
+      if (kn != kl && wv == (kn + dir) % NW) load_inv(kn + dir, fwd);
+    }
+    __syncthreads();
+  };
+  if (PASSES & 2) pass(true);
+  if (PASSES & 1) pass(false);
+
+  // the result out through LDS: one column tile at a time, rows contiguous
+  double nd = 0.0;
 #pragma unroll
   for (int c = 0; c < KT; ++c) {
     if (c >= ncol) continue;
@@ -2579,13 +2622,30 @@ __global__ void __launch_bounds__(64 * NW, 1) k_backsolve_big(Geom g, const doub
       const double v = Xs[r * 17 + cc];
       if (o.mode == BACK_UI) {
         o.ui[(size_t)leaf * ni + r] = v;
-      } else if (col < nb) {
-        o.Xt[((size_t)leaf * nb + col) * ni + r] = v;
       } else {
-        o.h[(size_t)leaf * ni + r] = v;
+        double *dst = (col < nb) ? o.Xt + ((size_t)leaf * nb + col) * ni + r
+                                 : o.h + (size_t)leaf * ni + r;
+        if (o.mode == BACK_STORE) {
+          *dst = v;
+        } else {
+          *dst += v;
+          nd += v * v;
+        }
       }
     }
     __syncthreads();
+  }
+  if (o.mode == BACK_ACCUM) {
+    double *red = Xs;   // the staging is free again
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
+    if (lane == 0) red[wv] = nd;
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0.0;
+      for (int w = 0; w < NW; ++w) a += red[w];
+      o.norms[kNormStride * (size_t)leaf + 16 + blockIdx.y] = a;
+    }
   }
 }
 
@@ -3711,9 +3771,10 @@ hipError_t launch_solve_rr(const Geom &g, int nleaf, const T *M, const int *piv,
   return launch_solve_rr_t<T, 16, 5, NW, MW>(g, nleaf, M, piv, o, s, sel);
 }
 
-// HPS_BACKSOLVE_BIG=0 turns the register-resident solve of the FP64 work
+// HPS_BACKSOLVE_BIG=0 turns the register-resident solves of the work
 // matrices above 256 rows off (the streaming solve then serves them).
-// Measured: 3.72 against 7.17 ms at 912 rows, 1.24 against 1.78 ms at 336.
+// Measured (FP64 back substitution): 3.72 against 7.17 ms at 912 rows, 1.24
+// against 1.78 ms at 336.
 bool backsolve_big_enabled() {
   static const bool on = [] {
     const char *v = std::getenv("HPS_BACKSOLVE_BIG");
@@ -3722,31 +3783,37 @@ bool backsolve_big_enabled() {
   return on;
 }
 
-bool backsolve_big_applies(const Geom &g, bool fp32, int mode) {
-  return !fp32 && g.R > 256 && g.RT <= 8 * 8 && (size_t)g.R * 17 <= 8 * 8 * 256 &&
-         (mode == BACK_STORE || mode == BACK_UI) && backsolve_big_enabled();
+// The register-resident solves for work matrices above 256 rows: FP64
+// factors (back substitution), and FP32 factors (back substitution, and the
+// refinement correction's forward and backward passes in one launch).
+bool solve_big_applies(const Geom &g) {
+  return g.R > 256 && g.RT <= 8 * 8 && (size_t)g.R * 17 <= 8 * 8 * 256 &&
+         (g.CT - g.RT + 1) / 2 <= kNormStride - 16 && backsolve_big_enabled();
 }
 
-hipError_t launch_backsolve_big(const Geom &g, int nleaf, double *M, const int *piv,
-                                const BackOut &o, hipStream_t s, const Sel &sel) {
-  hipLaunchKernelGGL(k_inv_udiag<double>, dim3(nleaf, (g.RT + 15) / 16), dim3(256), 0, s, g, M,
-                     piv);
+template <typename T, int PASSES>
+hipError_t launch_solve_big(const Geom &g, int nleaf, T *M, const int *piv, const BackOut &o,
+                            hipStream_t s, const Sel &sel) {
+  hipLaunchKernelGGL((k_inv_udiag<T, PASSES>), dim3(nleaf, (g.RT + 15) / 16), dim3(256), 0, s, g,
+                     M, piv, sel);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = backsolve_big_lds<8, 8>(g.R);
+  const size_t lds = solve_big_lds<T, 8, 8>(g.R);
   if (lds > kLdsLimit) return hipErrorInvalidValue;
-  e = set_lds(k_backsolve_big<8, 8>, lds);
+  e = set_lds(k_solve_big<T, 8, 8, PASSES>, lds);
   if (e != hipSuccess) return e;
   const int nck = (g.CT - g.RT + 1) / 2;
-  hipLaunchKernelGGL((k_backsolve_big<8, 8>), dim3(nleaf, nck), dim3(512), lds, s, g,
-                     (const double *)M, piv, o, sel);
+  hipLaunchKernelGGL((k_solve_big<T, 8, 8, PASSES>), dim3(nleaf, nck), dim3(512), lds, s, g,
+                     (const T *)M, piv, o, sel);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const Geom &g, int nleaf, bool fp32, void *M, const int *piv,
                             const int *rstep, const BackOut &o, hipStream_t s, const Sel &sel) {
-  if (backsolve_big_applies(g, fp32, o.mode))
-    return launch_backsolve_big(g, nleaf, (double *)M, piv, o, s, sel);
+  if (solve_big_applies(g)) {
+    if (fp32) return launch_solve_big<float, 1>(g, nleaf, (float *)M, piv, o, s, sel);
+    return launch_solve_big<double, 1>(g, nleaf, (double *)M, piv, o, s, sel);
+  }
   if (solve_rr_applies(g)) {
     if (fp32) return launch_solve_rr<float>(g, nleaf, (const float *)M, piv, o, s, sel);
     return launch_solve_rr<double>(g, nleaf, (const double *)M, piv, o, s, sel);
@@ -3786,7 +3853,14 @@ hipError_t launch_refine_solve(const Geom &g, int nleaf, void *M, const int *piv
     if (nch != 1) return hipErrorInvalidValue;
     return launch_solve_cols(g, nleaf, (const float *)M, piv, o, s);
   }
+  if (solve_big_applies(g)) return launch_solve_big<float, 3>(g, nleaf, (float *)M, piv, o, s, Sel());
   return launch_trisolve<float, 3>(g, nleaf, (float *)M, piv, rstep, o, s, Sel(), nch);
+}
+
+int refine_solve_chunks(const Geom &g, int nch) {
+  if (solve_rr_applies(g)) return 1;
+  if (solve_big_applies(g)) return (g.CT - g.RT + 1) / 2;
+  return nch;
 }
 
 // The first two refinement iterations cover every leaf, or about half of
