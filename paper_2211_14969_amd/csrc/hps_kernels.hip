@@ -235,6 +235,49 @@ __device__ __forceinline__ double build_elem(const Geom &g, LeafScale sc, int le
   return v;
 }
 
+// Sparse formation of a 16-column tile of W = [A_ii | A_ib ...] (no mixed
+// term): the column of node (k, l) is nonzero only in the rows of interior
+// nodes on its two grid lines, (i, l) and (k, j), and a boundary node's
+// column only on the one line that enters the leaf.  A tile qualifies when
+// none of its columns is dense (the body-load or re-factor column).
+__device__ __forceinline__ bool build_tile_sparse(const Geom &g, const BuildSrc &bs, int col0) {
+  if (g.a12) return false;
+  const int dense = bs.mode == RHS_CONDENSE ? (bs.f ? g.R + g.nb : -1) : g.R;
+  return dense < col0 || dense >= col0 + 16;
+}
+
+// Entry q (0 <= q < 2m - 1) of column col's line list: the row node (i, j)
+// and the column node (k, l); false when the column has no such entry (the
+// right-hand-side columns hold A_ib only when condensing).
+__device__ __forceinline__ bool line_entry(const Geom &g, const BuildSrc &bs, int col, int q,
+                                           int &i, int &j, int &k, int &l) {
+  const int m = g.m, p = g.p;
+  if (col < g.ni) {
+    k = col % m + 1;
+    l = col / m + 1;
+    if (q < m) {          // the x1-line through the node
+      i = q + 1;
+      j = l;
+    } else {              // the x2-line, the node itself already counted
+      i = k;
+      j = q - m + 1;
+      if (j >= l) ++j;
+    }
+    return true;
+  }
+  const int jr = col - g.R;
+  if (bs.mode != RHS_CONDENSE || jr < 0 || jr >= g.nb || q >= m) return false;
+  bnode(jr, m, p, k, l);
+  if (k == 0 || k == p - 1) {   // W / E side: the x1-line of its row
+    i = q + 1;
+    j = l;
+  } else {                      // S / N side: the x2-line of its column
+    i = k;
+    j = q + 1;
+  }
+  return true;
+}
+
 // Pivot search key of one candidate row: the magnitude's leading bits (exact
 // for FP32; the top 32 bits of the FP64 pattern, i.e. 20 mantissa bits, so
 // candidates within a relative 2^-20 of the largest count as ties) above the
@@ -1219,6 +1262,138 @@ __device__ __forceinline__ void rr_panel_columns(float (&v)[4][16], unsigned &ac
   (rr_panel_column<Cs>(v, act, lane, k, prb, pv, rst, zp), ...);
 }
 
+// panel_wg with the panel rows in registers: thread t holds panel rows t,
+// t + NT, ... (all 16 columns), so each column's update is register
+// arithmetic instead of LDS traffic.  Before each barrier every wavefront
+// publishes its candidate for the coming column, a DPP maximum of the
+// packed pivot key (magnitude's leading bits, then the complemented row:
+// ties to the lowest row, as in the single-wavefront panel), with the
+// candidate row's values, stored by the lane that holds the row; after it
+// every thread takes the largest of the wavefronts' keys, updates its rows
+// and scans the next column.  Slots alternate by column parity.  The rows
+// go back to LDS at the end, where the rest of the factorisation reads them.
+struct PanelSlots {
+  unsigned long long *key;   // [2][NW] the wavefronts' candidate keys (0: none)
+  void *vals;                // [2][NW][16] the candidate rows' values
+};
+
+template <typename T, int NT, int RPT, int C>
+__device__ __forceinline__ void preg_publish(const T (&v)[RPT][16], const bool (&act)[RPT],
+                                             int tid, const PanelSlots &ps) {
+  constexpr int NW = NT / 64;
+  const int lane = tid & 63, wv = tid >> 6, slot = (C & 1) * NW + wv;
+  unsigned long long key = 0;
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    if (act[h]) {
+      const unsigned long long kh = pivot_key(v[h][C], tid + h * NT);
+      key = kh > key ? kh : key;
+    }
+  }
+  const unsigned long long wk = wave_max_u64(key);
+  const int wr = 0x7fffffff - (int)(unsigned)(wk & 0xffffffffu);   // INT_MAX: no active row
+  T *dst = (T *)ps.vals + slot * 16;
+  if (lane == 0) ps.key[slot] = wk;
+  if (wk == 0 && lane < 16) dst[lane] = T(0);
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    if (tid + h * NT == wr) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) dst[cc] = v[h][cc];
+    }
+  }
+}
+
+template <typename T, int NT, int RPT, int C>
+__device__ __forceinline__ void preg_column(T (&v)[RPT][16], bool (&act)[RPT], int tid, int R,
+                                            int k, int *pv, int *rst, int *zeroPiv,
+                                            const PanelSlots &ps) {
+  constexpr int NW = NT / 64;
+  const int s0 = (C & 1) * NW;
+  const T *vals = (const T *)ps.vals;
+  // every wavefront's key and candidate pivot value at once (one LDS round
+  // trip); keys carry distinct rows, so the largest is unique
+  unsigned long long best = ps.key[s0];
+  T pval = vals[s0 * 16 + C];
+  int bw = 0;
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    const unsigned long long ok = ps.key[s0 + w];
+    const T ov = vals[(s0 + w) * 16 + C];
+    if (ok > best) {
+      best = ok;
+      pval = ov;
+      bw = w;
+    }
+  }
+  // at least 16 - C rows are active, so the key names a valid row; the
+  // clamp only guards the memory access
+  const int bi = 0x7fffffff - (int)(unsigned)(best & 0xffffffffu);
+  const int pr = (bi >= 0 && bi < R) ? bi : R - 1;
+  const T *prow = vals + (s0 + bw) * 16;
+  if (tid == 0) {
+    pv[C] = pr;
+    rst[pr] = k;
+    if (pval == T(0) && *zeroPiv == 0) *zeroPiv = k * 16 + C + 1;
+  }
+  const T inv = (pval != T(0)) ? T(1) / pval : T(0);
+  bool upd[RPT];
+  T l[RPT];
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const bool mine = tid + h * NT == pr;
+    upd[h] = act[h] && !mine;
+    if (mine) act[h] = false;
+    l[h] = v[h][C] * inv;
+    if (upd[h]) v[h][C] = l[h];
+  }
+#pragma unroll
+  for (int cc = C + 1; cc < 16; ++cc) {
+    const T u = prow[cc];
+#pragma unroll
+    for (int h = 0; h < RPT; ++h)
+      if (upd[h]) v[h][cc] -= l[h] * u;
+  }
+  if constexpr (C + 1 < 16) preg_publish<T, NT, RPT, C + 1>(v, act, tid, ps);
+  __syncthreads();
+}
+
+template <typename T, int NT, int RPT, int... Cs>
+__device__ __forceinline__ void preg_columns(T (&v)[RPT][16], bool (&act)[RPT], int tid, int R,
+                                             int k, int *pv, int *rst, int *zeroPiv,
+                                             const PanelSlots &ps,
+                                             std::integer_sequence<int, Cs...>) {
+  (preg_column<T, NT, RPT, Cs>(v, act, tid, R, k, pv, rst, zeroPiv, ps), ...);
+}
+
+template <typename T, int NT, int RPT>
+__device__ __forceinline__ void panel_wg_regs(T *P, int R, int k, int *pv, int *rst, int *zeroPiv,
+                                              const PanelSlots &ps) {
+  const int tid = threadIdx.x;
+  T v[RPT][16];
+  bool act[RPT];
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const int r = tid + h * NT;
+    act[h] = r < R && rst[r] == kInfoActive;
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) v[h][cc] = r < R ? P[r * kPST + cc] : T(0);
+  }
+  preg_publish<T, NT, RPT, 0>(v, act, tid, ps);
+  __syncthreads();
+  preg_columns<T, NT, RPT>(v, act, tid, R, k, pv, rst, zeroPiv, ps,
+                           std::make_integer_sequence<int, 16>());
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const int r = tid + h * NT;
+    if (r < R) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) P[r * kPST + cc] = v[h][cc];
+    }
+  }
+  __syncthreads();
+}
+
 // Workgroup barrier ordering LDS accesses only: global loads still in flight
 // (the next step's prefetched operands) are not waited for, as they would be
 // by __syncthreads().
@@ -1312,9 +1487,31 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
 #pragma unroll
     for (int c = 0; c < KT; ++c) {
       if (c < ncol) {
-        for (int e = tid; e < R * 16; e += NT) {
-          const int pos = e >> 4, cc = e & 15;
-          P[pos * kPST + cc] = (T)build_elem(g, sc, leaf, bs, ord[pos], 16 * (c0 + c) + cc);
+        const int col0 = 16 * (c0 + c);
+        if (build_tile_sparse(g, bs, col0)) {
+          // the operator's columns reach only the grid lines through their
+          // node: zeros (and the padding rows' identity) first, then the
+          // line entries at their rows' positions
+          for (int e = tid; e < R * 16; e += NT) {
+            const int pos = e >> 4, cc = e & 15, r = ord[pos];
+            P[pos * kPST + cc] = (r >= g.ni && r == col0 + cc) ? T(1) : T(0);
+          }
+          __syncthreads();
+          const int per = 2 * g.m - 1;
+          for (int e = tid; e < 16 * per; e += NT) {
+            const int cc = e / per, q = e - cc * per;
+            int i, j, k, l;
+            if (line_entry(g, bs, col0 + cc, q, i, j, k, l)) {
+              const int r = (j - 1) * g.m + (i - 1);
+              P[where[r] * kPST + cc] =
+                  (T)opval(g, g.D, g.D2, sc, (size_t)leaf * g.p * g.p, i, j, k, l);
+            }
+          }
+        } else {
+          for (int e = tid; e < R * 16; e += NT) {
+            const int pos = e >> 4, cc = e & 15;
+            P[pos * kPST + cc] = (T)build_elem(g, sc, leaf, bs, ord[pos], 16 * (c0 + c) + cc);
+          }
         }
       }
       __syncthreads();
@@ -1372,44 +1569,57 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
     // through the positions straight into this wavefront's LDS slot i
     // (global-to-LDS loads: no registers held while they are in flight; each
     // lane's 16 bytes land at the slot base + 16 lane, i.e. the tile in
-    // row-major order)
-    auto dma_a = [&](int i, int j) {
-      const int t = wv + NW * i;
-      T *dst = Abuf + (size_t)(wv * RTW + i) * 256;
-      constexpr int per = 1024 / (int)sizeof(T);   // elements per instruction
+    // row-major order).  The positions do not move during the updates, so
+    // each lane's source offsets (row part) are formed once per block column.
+    constexpr int kPer = 1024 / (int)sizeof(T);   // elements per instruction
+    constexpr int kIns = 256 / kPer;               // instructions per tile
+    int roff[RTW][kIns];
 #pragma unroll
-      for (int h = 0; h < 256 / per; ++h) {
-        const int e = h * per + lane * (16 / (int)sizeof(T));
-        const T *src = Ml + tix<T>(ord[16 * t + (e >> 4)], 16 * j + (e & 15), CT);
+    for (int i = 0; i < RTW; ++i) {
+      const int t = min(wv + NW * i, RT - 1);
+#pragma unroll
+      for (int h = 0; h < kIns; ++h) {
+        const int e = h * kPer + lane * (16 / (int)sizeof(T));
+        const int row = ord[16 * t + (e >> 4)];
+        roff[i][h] = (int)tix<T>(row, e & 15, CT);
+      }
+    }
+    auto dma_a = [&](int i, int j) {
+      T *dst = Abuf + (size_t)(wv * RTW + i) * 256;
+#pragma unroll
+      for (int h = 0; h < kIns; ++h) {
+        const T *src = Ml + roff[i][h] + (size_t)j * 256;
         __builtin_amdgcn_global_load_lds((const void *)src,
-                                         (__attribute__((address_space(3))) void *)(dst + h * per),
+                                         (__attribute__((address_space(3))) void *)(dst + h * kPer),
                                          16, 0, 0);
       }
     };
-    // the A operand of tile i (negated) from its slot.  In MFMA step kc lane
-    // group lr contracts over index 4 lr + kc (the same pairing in B), so a
-    // lane reads four consecutive values.
+    // the A operand of tile i from its slot.  In MFMA step kc lane group lr
+    // contracts over index 4 lr + kc (the same pairing in B), so a lane reads
+    // four consecutive values.
     auto read_a = [&](int i, T (&a)[4]) {
       const T *src = Abuf + (size_t)(wv * RTW + i) * 256 + lc * 16 + 4 * lr;
 #pragma unroll
-      for (int kc = 0; kc < 4; ++kc) a[kc] = -src[kc];
+      for (int kc = 0; kc < 4; ++kc) a[kc] = src[kc];
     };
-    // tile i takes step j's update; its slot then refills with panel jn's
-    // multipliers at once (when the tile needs them), so that load is in
-    // flight during the rest of the step
+    // tile i takes step j's update (b holds -U); its slot then refills with
+    // panel jn's multipliers (when the tile needs them), so that load is in
+    // flight during the rest of the step.  The empty asm consumes the A
+    // operand before the refill: the slot's reads have completed, and no
+    // memory operation moves above it.
     auto mma = [&](int i, const T (&b)[KT][4], int jn) {
       T a[4];
       read_a(i, a);
-      if (jn >= 0 && wv + NW * i > jn) {
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the slot has been read
-        dma_a(i, jn);
-      }
 #pragma unroll
       for (int c = 0; c < KT; ++c) {
         if (c < ncol) {
 #pragma unroll
           for (int kc = 0; kc < 4; ++kc) acc[i][c] = Mfma<T>::op(a[kc], b[c][kc], acc[i][c]);
         }
+      }
+      if (jn >= 0 && wv + NW * i > jn) {
+        asm volatile("" ::"v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]) : "memory");
+        dma_a(i, jn);
       }
     };
 
@@ -1444,7 +1654,7 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
 #pragma unroll
       for (int c = 0; c < KT; ++c) {
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? U[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
+        for (int kc = 0; kc < 4; ++kc) b[c][kc] = c < ncol ? -U[(4 * lr + kc) * KW + 16 * c + lc] : T(0);
       }
       const int jn = j + 1;
       const int jload = jn < nprev ? jn : -1;
@@ -1468,6 +1678,24 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
       }
     }
     __syncthreads();
+
+    // the rows retired by earlier block columns (positions below 16 c0) now
+    // hold their final U values: out at once, so that the panel tile's
+    // registers are free while its panel is eliminated
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+      const int t = wv + NW * i;
+      if (t >= c0 || t >= RT) continue;
+#pragma unroll
+      for (int c = 0; c < KT; ++c) {
+        if (c >= ncol) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = ord[16 * t + Tile<T>::crow(q, lane)];
+          Ml[tix<T>(row, 16 * (c0 + c) + lc, CT)] = (T)acc[i][c][q];
+        }
+      }
+    }
 
     // this block column's own panels, in turn.  The panel being factored is
     // always register tile 0: after each panel the block column's tiles
@@ -1498,7 +1726,12 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
               wave_lds_fence<T>();
             }
           } else {
-            panel_wg<T, NT>(P, Rr, k, pv, pst, zeroPiv, redv, redi);
+            // the panel's slots in the U-row buffer (free until the panel is done)
+            static_assert(16 * NW * RTW <= 64 * NW * ((RTW + 3) / 4), "panel rows per thread");
+            PanelSlots ps;
+            ps.key = (unsigned long long *)Ub;
+            ps.vals = (void *)(ps.key + 2 * NW);
+            panel_wg_regs<T, NT, (RTW + 3) / 4>(P, Rr, k, pv, pst, zeroPiv, ps);
           }
           if (wv == 0) {
             linv16<T>(P, pv, Lk, lane);
@@ -1513,11 +1746,11 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
 #pragma unroll
           for (int i = 0; i < RTW; ++i) {
             const int t = wv + NW * i;
-            if (t >= c0 && t < RT) {
+            const bool live = t >= c0 && t < RT;
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
-                acc[i][0][q] = (double)P[(16 * (t - c0) + Tile<T>::crow(q, lane)) * kPST + lc];
-            }
+            for (int q = 0; q < 4; ++q)
+              acc[i][0][q] = live ? (double)P[(16 * max(t - c0, 0) + Tile<T>::crow(q, lane)) * kPST + lc]
+                                  : 0.0;
           }
           if (s + 1 < ncol) {
             // raw pivot rows of the block's later column tiles (register
@@ -1583,11 +1816,12 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
       }
     }
 
-    // the block column, once, at the rows' places in the work matrix
+    // the rest of the block column, once, at the rows' places in the work
+    // matrix
 #pragma unroll
     for (int i = 0; i < RTW; ++i) {
       const int t = wv + NW * i;
-      if (t >= RT) continue;
+      if (t < c0 || t >= RT) continue;
 #pragma unroll
       for (int c = 0; c < KT; ++c) {
         if (c >= ncol) continue;
@@ -3611,11 +3845,11 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
                          int *info, int mode, const double *f, const double *ub, hipStream_t s,
                          const Sel &sel) {
   const BuildSrc bs{mode, f, ub};
-  // The left-looking factorisation is the FP64 default above 400 rows
-  // (p >= 23): measured 1.3x (p = 24) to 1.5x (p = 32) faster than panel
-  // pairs there for the whole condensation, slower at p <= 20, and slower in
-  // FP32 at every order (whose work matrices stream half the bytes).
-  if (g.tune_variant == 4 || (g.tune_variant == 0 && !fp32 && g.R > 400)) {
+  // The left-looking factorisation is the default above 400 rows (p >= 23):
+  // in FP64 measured 1.3x (p = 24) to 1.5x (p = 32) faster than panel pairs
+  // for the whole condensation, in FP32 1.3x at p = 32 (26.8 against 35.2
+  // ms), slower at p <= 20 in both.
+  if (g.tune_variant == 4 || (g.tune_variant == 0 && g.R > 400)) {
     if (fp32) return launch_factor_ll<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     return launch_factor_ll<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
   }
