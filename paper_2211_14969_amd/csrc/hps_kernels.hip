@@ -1490,13 +1490,12 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
         const int col0 = 16 * (c0 + c);
         if (build_tile_sparse(g, bs, col0)) {
           // the operator's columns reach only the grid lines through their
-          // node: zeros (and the padding rows' identity) first, then the
-          // line entries at their rows' positions
-          for (int e = tid; e < R * 16; e += NT) {
-            const int pos = e >> 4, cc = e & 15, r = ord[pos];
-            P[pos * kPST + cc] = (r >= g.ni && r == col0 + cc) ? T(1) : T(0);
-          }
+          // node: zeros first, then the padding rows' identity and the line
+          // entries at their rows' positions
+          for (int e = tid; e < R * 16; e += NT) P[(e >> 4) * kPST + (e & 15)] = T(0);
           __syncthreads();
+          if (tid < 16 && col0 + tid >= g.ni && col0 + tid < R)
+            P[where[col0 + tid] * kPST + tid] = T(1);
           const int per = 2 * g.m - 1;
           for (int e = tid; e < 16 * per; e += NT) {
             const int cc = e / per, q = e - cc * per;
