@@ -1526,20 +1526,14 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
     }
 
     // U rows of tile j (the pivots of panel j, in pivot order) from its
-    // current values, by the wavefront that owns the tile: through the LDS
-    // buffer `buf` (raw rows in, U rows out, where the others read them)
+    // current values, by the wavefront that owns the tile, into the LDS
+    // buffer `buf` where the others read them.  The tile's accumulators are
+    // the B operand as they stand: register kc holds row 4 kc + lr, the
+    // index L11^{-1} (the A operand) is paired with.
     auto make_u = [&](int j, T *buf, const T (&a)[4]) {
 #pragma unroll
       for (int i = 0; i < RTW; ++i) {
         if (wv + NW * i != j) continue;
-#pragma unroll
-        for (int c = 0; c < KT; ++c) {
-          if (c < ncol) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) buf[Tile<T>::crow(q, lane) * KW + 16 * c + lc] = (T)acc[i][c][q];
-          }
-        }
-        wave_lds_fence<T>();
         Acc u[KT];
 #pragma unroll
         for (int c = 0; c < KT; ++c) {
@@ -1547,11 +1541,9 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
           for (int q = 0; q < 4; ++q) u[c][q] = 0.0;
           if (c < ncol) {
 #pragma unroll
-            for (int kc = 0; kc < 4; ++kc)
-              u[c] = Mfma<T>::op(a[kc], buf[(4 * kc + lr) * KW + 16 * c + lc], u[c]);
+            for (int kc = 0; kc < 4; ++kc) u[c] = Mfma<T>::op(a[kc], (T)acc[i][c][kc], u[c]);
           }
         }
-        wave_lds_fence<T>();
 #pragma unroll
         for (int c = 0; c < KT; ++c) {
           if (c < ncol) {
@@ -1832,24 +1824,35 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
       }
     }
 
-    // the pivots of this block column take the positions 16 k + c
+    // the pivots of this block column take the positions 16 k + c; the rows
+    // they displace (those at the targets that are not pivots) take the
+    // pivots' places outside the targets, the n-th displaced row the n-th
+    // such place.  One wavefront, lane e moving pivot e.
     if (npan > 0) {
-      if (tid < 16 * npan) pvs[tid] = ord[16 * c0 + pvs[tid]];   // positions -> rows
-      __syncthreads();
-      if (tid == 0) {
-        for (int e = 0; e < 16 * npan; ++e) {
-          const int row = pvs[e], target = 16 * c0 + e, src = where[row];
-          const int other = ord[target];
-          ord[target] = row;
-          where[row] = target;
-          ord[src] = other;
-          where[other] = src;
+      if (wv == 0) {
+        const int nt = 16 * npan;
+        const bool on = lane < nt;
+        const int rel = on ? pvs[lane] : 0;               // pivot's position - 16 c0
+        const int row = on ? ord[16 * c0 + rel] : 0;
+        const int cur = on ? ord[16 * c0 + lane] : 0;     // the row at the target now
+        const bool disp = on && pst[lane] == kInfoActive;
+        const bool frees = on && rel >= nt;
+        const unsigned long long dm = __ballot(disp), fm = __ballot(frees);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int *moved = (int *)Ub;                            // free until the next block column
+        if (disp) moved[__popcll(dm & below)] = cur;
+        wave_lds_fence<T>();
+        if (on) {
+          ord[16 * c0 + lane] = row;
+          where[row] = 16 * c0 + lane;
+          piv[(size_t)wi * R + 16 * c0 + lane] = row;
+          rstep[(size_t)wi * R + row] = c0 + lane / 16;
         }
-      }
-      if (tid < 16 * npan) {
-        const int k = c0 + tid / 16;
-        piv[(size_t)wi * R + 16 * c0 + tid] = pvs[tid];
-        rstep[(size_t)wi * R + pvs[tid]] = k;
+        if (frees) {
+          const int other = moved[__popcll(fm & below)];
+          ord[16 * c0 + rel] = other;
+          where[other] = 16 * c0 + rel;
+        }
       }
       __syncthreads();
     }
