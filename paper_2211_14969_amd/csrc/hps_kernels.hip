@@ -2688,17 +2688,28 @@ constexpr size_t solve_big_lds(int R) {
 
 template <typename T, int NW, int RTW, int PASSES>
 __global__ void __launch_bounds__(64 * NW, 1) k_solve_big(Geom g, const T *M, const int *piv,
-                                                         BackOut o, Sel sel) {
+                                                         BackOut o, Sel sel, int nleaf, int nck) {
   constexpr int NT = 64 * NW, KT = 2, KW = 16 * KT;
   constexpr int kPer = 1024 / (int)sizeof(T);   // elements per gather instruction
   constexpr int kIns = 256 / kPer;               // instructions per tile
   extern __shared__ __align__(16) unsigned char smem[];
-  const int wi = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  int leaf;
-  if (!resolve_leaf(sel, leaf)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // XCD-aware order: workgroups are dealt to the eight XCDs round-robin by
+  // id, so the column chunks of one leaf take ids of one residue mod 8 and
+  // run together on one XCD, whose L2 then serves the leaf's factor tiles
+  // to all of them after one read from HBM
+  const int xcd = (int)blockIdx.x & 7, grp = (int)blockIdx.x >> 3;
+  const int chunk = grp % nck, wi = (grp / nck) * 8 + xcd;
+  if (wi >= nleaf) return;
+  int leaf = wi;
+  if (sel.list) {
+    const int slot = sel.slot0 + wi;
+    if (slot >= *sel.count) return;
+    leaf = sel.list[slot];
+  }
   if (o.skip && o.skip[leaf]) return;
   const int R = g.R, RT = g.RT, CT = g.CT, ni = g.ni, nb = g.nb, NCT = CT - RT;
-  const int c0 = blockIdx.y * KT;              // first right-hand-side column tile
+  const int c0 = chunk * KT;                   // first right-hand-side column tile
   const int ncol = min(KT, NCT - c0);
   if (ncol <= 0) return;
   const size_t slot_bytes = sizeof(T) * (size_t)NW * RTW * 256;
@@ -2880,7 +2891,7 @@ __global__ void __launch_bounds__(64 * NW, 1) k_solve_big(Geom g, const T *M, co
     if (tid == 0) {
       double a = 0.0;
       for (int w = 0; w < NW; ++w) a += red[w];
-      o.norms[kNormStride * (size_t)leaf + 16 + blockIdx.y] = a;
+      o.norms[kNormStride * (size_t)leaf + 16 + chunk] = a;
     }
   }
 }
@@ -4039,8 +4050,9 @@ hipError_t launch_solve_big(const Geom &g, int nleaf, T *M, const int *piv, cons
   e = set_lds(k_solve_big<T, 8, 8, PASSES>, lds);
   if (e != hipSuccess) return e;
   const int nck = (g.CT - g.RT + 1) / 2;
-  hipLaunchKernelGGL((k_solve_big<T, 8, 8, PASSES>), dim3(nleaf, nck), dim3(512), lds, s, g,
-                     (const T *)M, piv, o, sel);
+  const int groups = (nleaf + 7) / 8;
+  hipLaunchKernelGGL((k_solve_big<T, 8, 8, PASSES>), dim3(groups * 8 * nck), dim3(512), lds, s,
+                     g, (const T *)M, piv, o, sel, nleaf, nck);
   return hipGetLastError();
 }
 
