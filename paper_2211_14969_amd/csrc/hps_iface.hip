@@ -187,89 +187,228 @@ __global__ __launch_bounds__(256) void k_nd_leaf_transform(const LeafD *ld, cons
 // block is updated with FP64 MFMA in strips of 16 x 64.  The final row order
 // is written to `perm` (row i of P F_ss is row perm[i] of F_ss).
 // ---------------------------------------------------------------------------
+// Workspace of the register-resident panel elimination behind the callers'
+// own LDS: the wavefronts' candidate keys and rows (two slots by column
+// parity), the pivots as panel rows, and the row order while the panel's
+// exchanges are formed.
+struct PanelSlots {
+  unsigned long long *key;   // [2][NW] candidate keys (0: none)
+  double *vals;              // [2][NW][16] candidate rows' values
+  int *pivo;                 // [16] pivot of each column as a panel row (before exchanges)
+  int *at, *where;           // [rows] panel row at each place, place of each panel row
+};
+
+size_t panel_slot_bytes(int n) {
+  const int nw = kFactorThreads / 64;
+  return 16 + sizeof(unsigned long long) * 2 * nw + sizeof(double) * 2 * nw * 16 +
+         sizeof(int) * (16 + 2 * (size_t)n);
+}
+
+__device__ __forceinline__ PanelSlots panel_slots(void *end_of_callers) {
+  constexpr int NW = kFactorThreads / 64;
+  const size_t a = ((size_t)end_of_callers + 15) & ~(size_t)15;
+  PanelSlots ps;
+  ps.key = (unsigned long long *)a;
+  ps.vals = (double *)(ps.key + 2 * NW);
+  ps.pivo = (int *)(ps.vals + 2 * NW * 16);
+  ps.at = ps.pivo + 16;
+  ps.where = nullptr;   // set by the caller from the row count
+  return ps;
+}
+
 size_t getrf_lds(int n) {
   const int n16 = (n + 15) & ~15;
   const int nw = kFactorThreads / 64;
-  return sizeof(double) * ((size_t)n16 * 16 + nw) + sizeof(int) * (nw + 16 + (size_t)n + 1);
+  return sizeof(double) * ((size_t)n16 * 16 + nw) + sizeof(int) * (nw + 16 + (size_t)n + 1) +
+         panel_slot_bytes(n);
+}
+
+// Pivot search key of a panel row: the magnitude's leading bits (the top 32
+// of the FP64 pattern: exponent and 20 mantissa bits; NaN above infinity),
+// then the complemented row, so that the maximum is unique and near-ties
+// go to the lowest row.  0 marks "no candidate".
+__device__ __forceinline__ unsigned long long nd_key(double v, int r) {
+  const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
+  return ((unsigned long long)hi << 32) | (unsigned)(0x7fffffff - r);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long nd_dpp_max(unsigned long long v) {
+  const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+  const unsigned long long o = ((unsigned long long)(unsigned)ohi << 32) | (unsigned)olo;
+  return o > v ? o : v;
+}
+
+// Wavefront maximum (quad permutations, row shifts, the row broadcasts of
+// lanes 15 and 31; lane 63 ends with it), read back to every lane.
+__device__ __forceinline__ unsigned long long nd_wave_max(unsigned long long v) {
+  v = nd_dpp_max<0xb1, 0xf>(v);
+  v = nd_dpp_max<0x4e, 0xf>(v);
+  v = nd_dpp_max<0x114, 0xf>(v);
+  v = nd_dpp_max<0x118, 0xf>(v);
+  v = nd_dpp_max<0x142, 0xa>(v);
+  v = nd_dpp_max<0x143, 0xc>(v);
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Each wavefront's candidate for panel column C (over its active rows) and
+// that row's values, written by the lane that holds it.
+template <int NT, int RPT, int C>
+__device__ __forceinline__ void nd_publish(const double (&v)[RPT][16], const bool (&act)[RPT],
+                                           int tid, const PanelSlots &ps) {
+  constexpr int NW = NT / 64;
+  const int lane = tid & 63, wv = tid >> 6, slot = (C & 1) * NW + wv;
+  unsigned long long key = 0;
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    if (act[h]) {
+      const unsigned long long kh = nd_key(v[h][C], tid + h * NT);
+      key = kh > key ? kh : key;
+    }
+  }
+  const unsigned long long wk = nd_wave_max(key);
+  const int wr = 0x7fffffff - (int)(unsigned)(wk & 0xffffffffu);   // INT_MAX: none
+  double *dst = ps.vals + slot * 16;
+  if (lane == 0) ps.key[slot] = wk;
+  if (wk == 0 && lane < 16) dst[lane] = 0.0;
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    if (tid + h * NT == wr) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) dst[cc] = v[h][cc];
+    }
+  }
+}
+
+// Column C of the panel: the pivot is the largest of the wavefronts' keys;
+// every thread eliminates its active rows in registers and publishes the
+// next column's candidates before the one barrier.
+template <int NT, int RPT, int C>
+__device__ __forceinline__ void nd_column(double (&v)[RPT][16], bool (&act)[RPT], int tid,
+                                          int rows, int w, int c0, const PanelSlots &ps, int *zp) {
+  if (C >= w) return;
+  constexpr int NW = NT / 64;
+  const int s0 = (C & 1) * NW;
+  unsigned long long best = ps.key[s0];
+  double pval = ps.vals[s0 * 16 + C];
+  int bw = 0;
+#pragma unroll
+  for (int k = 1; k < NW; ++k) {
+    const unsigned long long ok = ps.key[s0 + k];
+    const double ov = ps.vals[(s0 + k) * 16 + C];
+    if (ok > best) {
+      best = ok;
+      pval = ov;
+      bw = k;
+    }
+  }
+  // at least one row is active, so the key names a valid row; the clamp
+  // only guards the memory accesses
+  const int bi = 0x7fffffff - (int)(unsigned)(best & 0xffffffffu);
+  const int pr = (bi >= 0 && bi < rows) ? bi : 0;
+  const double *prow = ps.vals + (s0 + bw) * 16;
+  if (tid == 0) {
+    ps.pivo[C] = pr;
+    if (!(fabs(pval) > 0.0) && *zp == 0) *zp = c0 + C + 1;
+  }
+  const bool doit = pval != 0.0;
+  const double inv = doit ? 1.0 / pval : 0.0;
+  bool upd[RPT];
+  double l[RPT];
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const bool mine = tid + h * NT == pr;
+    upd[h] = doit && act[h] && !mine;
+    if (mine) act[h] = false;
+    l[h] = v[h][C] * inv;
+    if (upd[h]) v[h][C] = l[h];
+  }
+#pragma unroll
+  for (int cc = C + 1; cc < 16; ++cc) {
+    const double u = prow[cc];
+#pragma unroll
+    for (int h = 0; h < RPT; ++h)
+      if (upd[h]) v[h][cc] -= l[h] * u;
+  }
+  if constexpr (C + 1 < 16) nd_publish<NT, RPT, C + 1>(v, act, tid, ps);
+  __syncthreads();
+}
+
+template <int NT, int RPT, int... Cs>
+__device__ __forceinline__ void nd_columns(double (&v)[RPT][16], bool (&act)[RPT], int tid,
+                                           int rows, int w, int c0, const PanelSlots &ps, int *zp,
+                                           std::integer_sequence<int, Cs...>) {
+  (nd_column<NT, RPT, Cs>(v, act, tid, rows, w, c0, ps, zp), ...);
 }
 
 // One 16-column panel of the LU of an n x n row-major A, columns c0 ..
-// c0+15: the panel factored in LDS (P, [n16][16]) with the pivot rule of
-// LAPACK getrf (largest magnitude, ties to the lowest row), written back, its
-// row exchanges applied to every other column (and to `perm`, the row order:
-// row i of P A is row perm[i] of A), then U12 = L11^{-1} A12.  A zero (or
-// NaN) pivot sets *zp to its column (1-based) unless already set.  All
-// threads of the workgroup call it; it ends with a barrier.
+// c0+15, partial pivoting (largest magnitude by the leading 20 mantissa
+// bits, ties to the lowest panel row): the panel is eliminated with its
+// rows in registers (thread t holds panel rows t and t + NT, one barrier per
+// column), the pivots are then turned into the LAPACK sequence of row
+// exchanges (pivl; `perm` is the row order: row i of P A is row perm[i] of
+// A) and the rows placed accordingly in LDS (P, [n16][16]), the panel
+// written back, its exchanges applied to every other column, then U12 =
+// L11^{-1} A12.  A zero (or NaN) pivot sets *zp to its column (1-based)
+// unless already set.  All threads of the workgroup call it; it ends with a
+// barrier.
 template <int NT>
-__device__ void nd_panel(double *A, int n, int c0, double *P, double *redv, int *redi, int *pivl,
+__device__ void nd_panel(double *A, int n, int c0, double *P, const PanelSlots &ps0, int *pivl,
                          int *perm, int *zp) {
-  constexpr int NW = NT / 64;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int RPT = (kMaxSep + NT - 1) / NT;
+  const int tid = threadIdx.x;
   const int w = min(16, n - c0), rows = n - c0;
-  for (int e = tid; e < rows * 16; e += NT) {
-    const int r = e >> 4, c = e & 15;
-    P[e] = c < w ? A[(size_t)(c0 + r) * n + c0 + c] : 0.0;
+  PanelSlots ps = ps0;
+  ps.where = ps.at + rows;
+  double v[RPT][16];
+  bool act[RPT];
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const int r = tid + h * NT;
+    act[h] = r < rows;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[h][c] = (r < rows && c < w) ? A[(size_t)(c0 + r) * n + c0 + c] : 0.0;
+  }
+  nd_publish<NT, RPT, 0>(v, act, tid, ps);
+  __syncthreads();
+  nd_columns<NT, RPT>(v, act, tid, rows, w, c0, ps, zp, std::make_integer_sequence<int, 16>());
+  // the exchanges in LAPACK's order: at column lc the pivot's current place
+  // swaps with place lc
+  for (int i = tid; i < rows; i += NT) {
+    ps.at[i] = i;
+    ps.where[i] = i;
   }
   __syncthreads();
-  for (int lc = 0; lc < w; ++lc) {
-    double bv = -1.0;
-    int br = INT_MAX;
-    for (int r = lc + tid; r < rows; r += NT) {
-      const double a = fabs(P[r * 16 + lc]);
-      if (a > bv) {
-        bv = a;
-        br = r;
+  if (tid == 0) {
+    for (int lc = 0; lc < w; ++lc) {
+      const int pr = ps.pivo[lc], cur = ps.where[pr], a = ps.at[lc];
+      ps.at[lc] = pr;
+      ps.where[pr] = lc;
+      ps.at[cur] = a;
+      ps.where[a] = cur;
+      pivl[lc] = c0 + cur;
+      if (cur != lc) {
+        const int t = perm[c0 + lc];
+        perm[c0 + lc] = perm[c0 + cur];
+        perm[c0 + cur] = t;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int orow = __shfl_xor(br, off);
-      if (ov > bv || (ov == bv && orow < br)) {
-        bv = ov;
-        br = orow;
-      }
-    }
-    if (lane == 0) {
-      redv[wv] = bv;
-      redi[wv] = br;
-    }
-    __syncthreads();
-    double pv = redv[0];
-    int pr = redi[0];
-    for (int k = 1; k < NW; ++k) {
-      if (redv[k] > pv || (redv[k] == pv && redi[k] < pr)) {
-        pv = redv[k];
-        pr = redi[k];
-      }
-    }
-    // no candidate (the whole column NaN): keep the row, flag the pivot
-    if (pr >= rows) pr = lc;
-    if (pr != lc && tid < 16) {
-      const double a = P[lc * 16 + tid];
-      P[lc * 16 + tid] = P[pr * 16 + tid];
-      P[pr * 16 + tid] = a;
-    }
-    if (tid == 0) {
-      pivl[lc] = c0 + pr;
-      if (pr != lc) {
-        const int a = perm[c0 + lc];
-        perm[c0 + lc] = perm[c0 + pr];
-        perm[c0 + pr] = a;
-      }
-      if (!(pv > 0.0) && *zp == 0) *zp = c0 + lc + 1;
-    }
-    __syncthreads();
-    const double d = P[lc * 16 + lc];
-    if (d != 0.0) {
-      const double inv = 1.0 / d;
-      for (int r = lc + 1 + tid; r < rows; r += NT) {
-        const double l = P[r * 16 + lc] * inv;
-        P[r * 16 + lc] = l;
-        for (int j = lc + 1; j < w; ++j) P[r * 16 + j] -= l * P[lc * 16 + j];
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < RPT; ++h) {
+    const int r = tid + h * NT;
+    if (r < rows) {
+      const int d = ps.where[r];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) P[d * 16 + c] = v[h][c];
+    }
+  }
+  __syncthreads();
   // panel back, and its row exchanges applied to every other column
   for (int e = tid; e < rows * 16; e += NT) {
     const int r = e >> 4, c = e & 15;
@@ -323,12 +462,13 @@ __global__ __launch_bounds__(kFactorThreads) void k_nd_getrf(const Front *fr, in
   int *pivl = redi + NW;             // [16] pivot row of each panel column
   int *perm = pivl + 16;             // [n]
   int *zp = perm + n;                // first zero pivot (1-based), 0 if none
+  const PanelSlots ps = panel_slots(zp + 1);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < n; i += NT) perm[i] = i;
   if (tid == 0) *zp = 0;
   __syncthreads();
   for (int c0 = 0; c0 < n; c0 += 16) {
-    nd_panel<NT>(A, n, c0, P, redv, redi, pivl, perm, zp);
+    nd_panel<NT>(A, n, c0, P, ps, pivl, perm, zp);
     if (c0 + 16 >= n) break;
     // trailing update A22 -= L21 U12, strips of one row tile x four column tiles
     const int r0 = c0 + 16;
@@ -395,12 +535,13 @@ __global__ __launch_bounds__(kFactorThreads) void k_nd_panel(const Front *fr, in
   int *redi = (int *)(redv + NW);
   int *pivl = redi + NW;
   int *perm = ia + f.perm;
+  const PanelSlots ps = panel_slots(pivl + 16);
   if (c0 == 0) {
     for (int i = threadIdx.x; i < n; i += NT) perm[i] = i;
     if (threadIdx.x == 0) info[fi] = 0;
     __syncthreads();
   }
-  nd_panel<NT>(ar + f.fss, n, c0, P, redv, redi, pivl, perm, info + fi);
+  nd_panel<NT>(ar + f.fss, n, c0, P, ps, pivl, perm, info + fi);
 }
 
 __global__ __launch_bounds__(256) void k_nd_trail(const Front *fr, int first, double *ar,
