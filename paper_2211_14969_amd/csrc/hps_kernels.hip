@@ -3858,11 +3858,13 @@ hipError_t launch_factor(const Geom &g, int nleaf, bool fp32, void *M, int *piv,
                          int *info, int mode, const double *f, const double *ub, hipStream_t s,
                          const Sel &sel) {
   const BuildSrc bs{mode, f, ub};
-  // The left-looking factorisation is the default above 400 rows (p >= 23):
-  // in FP64 measured 1.3x (p = 24) to 1.5x (p = 32) faster than panel pairs
-  // for the whole condensation, in FP32 1.3x at p = 32 (26.8 against 35.2
-  // ms), slower at p <= 20 in both.
-  if (g.tune_variant == 4 || (g.tune_variant == 0 && g.R > 400)) {
+  // The left-looking factorisation is the default above 400 rows (p >= 23)
+  // in both precisions, and in FP64 from 177 rows (p >= 16): measured 1.3x
+  // (p = 24) to 1.5x (p = 32) faster than panel pairs for the whole
+  // condensation, in FP32 1.3x at p = 32 (26.8 against 35.2 ms); in FP64
+  // since the register-resident panels also 4.10 against 5.48 ms at p = 16
+  // and 8.35 against 8.91 at p = 20, while FP32 stays slower there.
+  if (g.tune_variant == 4 || (g.tune_variant == 0 && (g.R > 400 || (!fp32 && g.R > 176)))) {
     if (fp32) return launch_factor_ll<float>(g, nleaf, (float *)M, piv, rstep, info, bs, s, sel);
     return launch_factor_ll<double>(g, nleaf, (double *)M, piv, rstep, info, bs, s, sel);
   }
