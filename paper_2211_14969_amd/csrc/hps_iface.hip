@@ -645,10 +645,19 @@ __global__ __launch_bounds__(kSolveThreads) void k_nd_getrs(const Front *fr, int
     if (khi > klo) {
       d4 acc = {0.0, 0.0, 0.0, 0.0};
       const int arow = rb + (lane & 15);
-      for (int s = (klo >> 2) + wv; s < (khi >> 2); s += NW) {
-        const int kk = 4 * s + (lane >> 4);
-        const double a = (arow < n && kk < n) ? A[(size_t)arow * n + kk] : 0.0;
-        acc = mma(a, Bs[kk * 16 + (lane & 15)], acc);
+      // four contraction steps per round, their loads issued together
+      const int s1 = khi >> 2;
+      for (int s0 = (klo >> 2) + wv; s0 < s1; s0 += 4 * NW) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int s = s0 + u * NW, kk = 4 * s + (lane >> 4);
+          const bool ok = s < s1;
+          a[u] = (ok && arow < n && kk < n) ? A[(size_t)arow * n + kk] : 0.0;
+          b[u] = ok ? Bs[kk * 16 + (lane & 15)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = mma(a[u], b[u], acc);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) red[wv * 256 + q * 64 + lane] = acc[q];
