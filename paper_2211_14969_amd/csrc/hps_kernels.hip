@@ -1654,13 +1654,15 @@ __global__ void __launch_bounds__(64 * NW, MINB) k_factor_ll(Geom g, T *M, int *
 #pragma unroll
         for (int i = 0; i < RTW; ++i)
           if (wv + NW * i == jn) mma(i, b, jload);
-        make_u(jn, Ub + (jn & 1) * 16 * KW, lpre);
       }
 #pragma unroll
       for (int i = 0; i < RTW; ++i) {
         const int t = wv + NW * i;
         if (t > j && t < RT && !(ahead && t == jn)) mma(i, b, jload);
       }
+      // U_{j+1} last: tile j+1's products have long completed by then, so
+      // forming it stalls nothing
+      if (ahead) make_u(jn, Ub + (jn & 1) * 16 * KW, lpre);
       if (jn < nprev) {
         if (jn + 1 < nprev && wv == (jn + 1) % NW) {
 #pragma unroll
@@ -2834,13 +2836,13 @@ __global__ void __launch_bounds__(64 * NW, 1) k_solve_big(Geom g, const T *M, co
 #pragma unroll
         for (int i = 0; i < RTW; ++i)
           if (wv + NW * i == kn) mma(i, b, kload, fwd);
-        form(kn, dpre);
       }
 #pragma unroll
       for (int i = 0; i < RTW; ++i) {
         const int t = wv + NW * i;
         if (t < RT && (fwd ? t > k : t < k) && !(ahead && t == kn)) mma(i, b, kload, fwd);
       }
+      if (ahead) form(kn, dpre);   // last, when tile kn's products have completed
       if (kn != kl && wv == (kn + dir) % NW) load_inv(kn + dir, fwd);
     }
     __syncthreads();
