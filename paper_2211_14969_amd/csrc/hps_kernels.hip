@@ -3483,13 +3483,26 @@ __global__ void __launch_bounds__(256) k_schur(Geom g, const double *Xt, const d
   for (int c0 = 0; c0 < ncol; c0 += kSchurCols) {
     const int cw = min(kSchurCols, ncol - c0);
     __syncthreads();
-    for (int e = threadIdx.x; e < cw * ni; e += blockDim.x) {
-      const int c = e / ni, i = e - c * ni;
-      const int col = c0 + c;
-      double v = 0.0;
-      if (col < nb) v = Xl[(size_t)col * ni + i];
-      else if (h) v = h[(size_t)leaf * ni + i];
-      xs[c * ni + i] = v;
+    // the pass's columns of X are contiguous (then h): eight independent
+    // loads per thread in flight at a time
+    {
+      const int tot = cw * ni, nx = (min(c0 + cw, nb) - c0) * ni;
+      const double *src = Xl + (size_t)c0 * ni;
+      const double *hl = h ? h + (size_t)leaf * ni : nullptr;   // entry e - nx
+      constexpr int U = 8;
+      for (int e0 = threadIdx.x; e0 < tot; e0 += U * 256) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * 256;
+          v[u] = e < nx ? src[e] : ((e < tot && hl) ? hl[e - nx] : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * 256;
+          if (e < tot) xs[e] = v[u];
+        }
+      }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < nb * cw; e += blockDim.x) {
