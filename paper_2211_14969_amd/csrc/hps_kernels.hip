@@ -1311,18 +1311,25 @@ __device__ __forceinline__ void preg_column(T (&v)[RPT][16], bool (&act)[RPT], i
   constexpr int NW = NT / 64;
   const int s0 = (C & 1) * NW;
   const T *vals = (const T *)ps.vals;
-  // every wavefront's key and candidate pivot value at once (one LDS round
-  // trip); keys carry distinct rows, so the largest is unique
-  unsigned long long best = ps.key[s0];
-  T pval = vals[s0 * 16 + C];
+  // every wavefront's key and candidate pivot value at once: all loads
+  // issued before any is used (the empty asm keeps them together, one LDS
+  // round trip); keys carry distinct rows, so the largest is unique
+  unsigned long long kw[NW];
+  T vw[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    kw[w] = ps.key[s0 + w];
+    vw[w] = vals[(s0 + w) * 16 + C];
+  }
+  asm volatile("" ::: "memory");
+  unsigned long long best = kw[0];
+  T pval = vw[0];
   int bw = 0;
 #pragma unroll
   for (int w = 1; w < NW; ++w) {
-    const unsigned long long ok = ps.key[s0 + w];
-    const T ov = vals[(s0 + w) * 16 + C];
-    if (ok > best) {
-      best = ok;
-      pval = ov;
+    if (kw[w] > best) {
+      best = kw[w];
+      pval = vw[w];
       bw = w;
     }
   }
